@@ -1,0 +1,199 @@
+/*
+ * mxp.h -- C ABI of libmxp, a mixed-precision dense solver for one MI355X
+ * (gfx950): counter-based generation of a diagonally dominant matrix, LU
+ * without pivoting in low precision, and GMRES-based iterative refinement
+ * in FP64 that recovers a solution meeting the HPL backward-error test.
+ *
+ * Paper passages the calls follow (HPL-MxP, Dongarra and Luszczek 2025):
+ *   "Matrix Generation"      -- scalable generation; diagonal scaling that
+ *                               makes pivoting unnecessary.
+ *   "Algorithmic Framework"  -- LU in low precision (panel and triangular
+ *                               solves in 32-bit, Schur-complement update in
+ *                               16-bit with 32-bit accumulation, Figure 1),
+ *                               x0 from the factors, GMRES in 64-bit with the
+ *                               factors as a left preconditioner, at most 50
+ *                               iterations, HPL scaled residual < 16 with
+ *                               eps = 2^-53, balancing/scaling allowed and
+ *                               undone at the end.
+ *
+ * Conventions for every call:
+ *   - Matrices are column-major.  Leading dimensions and sizes are int64.
+ *   - Pointers named A, B, X, diag, a_inf, aux, work are DEVICE pointers
+ *     (memory on the current HIP device) owned by the caller; the library
+ *     never frees them and never keeps them after the call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Work is enqueued on it.  A call returns after enqueueing unless its
+ *     comment says it synchronises.
+ *   - Return value: MXP_OK (0); a negative code for an argument or runtime
+ *     error, in which case nothing was enqueued (MXP_EINVAL, MXP_EWORKSPACE)
+ *     or a HIP call failed (MXP_EHIP, text in mxp_last_error()); a positive
+ *     code for a numerical outcome (MXP_ESINGULAR, MXP_ENOCONV,
+ *     MXP_ECRITERION).  No C++ exception crosses this interface.
+ *   - The library allocates no device memory in mxp_generate, mxp_factor
+ *     and mxp_solve_ir: scratch space is passed in (`work`) and sized by
+ *     the matching *_bytes query.
+ */
+#ifndef MXP_H
+#define MXP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element formats */
+typedef enum {
+    MXP_F64 = 0,
+    MXP_F32 = 1,
+    MXP_F16 = 2,     /* IEEE binary16 */
+    MXP_BF16 = 3,    /* bfloat16 */
+    MXP_F8E4M3 = 4   /* OCP fp8 e4m3fn (max 448, no infinities) */
+} mxp_dtype;
+
+/* status codes */
+enum {
+    MXP_OK = 0,
+    MXP_EINVAL = -1,      /* bad argument (size, dtype combination, NULL pointer) */
+    MXP_EWORKSPACE = -2,  /* work buffer smaller than the *_bytes query says */
+    MXP_EHIP = -3,        /* a HIP runtime call failed; see mxp_last_error() */
+    MXP_ESINGULAR = 1,    /* zero or non-finite pivot; *info = 1-based column */
+    MXP_ENOCONV = 2,      /* refinement needed more than max_iters iterations */
+    MXP_ECRITERION = 3    /* refinement stopped but scaled residual >= tol */
+};
+
+/* input scaling applied before the factorisation ("Algorithmic Framework":
+ * balancing and scaling are allowed, their time counts, and their effect is
+ * undone at the end) */
+enum {
+    MXP_SCALE_NONE = 0,
+    MXP_SCALE_ROW_EQUIL = 1  /* row i scaled by the power of two nearest 1/A[i,i] */
+};
+
+/* text of the last MXP_EHIP / MXP_EINVAL error of the calling thread */
+const char *mxp_last_error(void);
+
+/* library version string */
+const char *mxp_version(void);
+
+/*
+ * mxp_generate -- "Matrix Generation".
+ * Generates A (n x n) and B (n x nrhs) from `seed`:
+ *   A[i,j] = k(i,j) * 2^-32 - 1/2 for i != j, with k the 32-bit Philox4x32-10
+ *            draw of stream 0 at counter (i, j/4, 0, 0), word j%4, key =
+ *            (seed low 32 bits, seed high 32 bits);
+ *   A[i,i] = sum over ALL j of |k(i,j) * 2^-32 - 1/2| (computed exactly);
+ *   B[i,r] = draw of stream 1 at (i, r) mapped the same way.
+ * A is written in the storage format `store` (MXP_F32, MXP_F16, MXP_BF16),
+ * each entry rounded to nearest even from its exact value; lda >= n.
+ * A may be NULL (nothing stored: the solver regenerates A on the fly).
+ * B (FP64, ldb >= n) may be NULL when nrhs == 0.
+ * diag (FP64, n entries): the exact diagonal; required.
+ * a_inf (FP64, 1 entry): ||A||_inf of the exact matrix; required.
+ * Asynchronous on `stream`.  n >= 1, n < 2^31.
+ */
+int mxp_generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void *A, int64_t lda,
+                 double *B, int64_t ldb, double *diag, double *a_inf, void *stream);
+
+/*
+ * Factorisation -- "Algorithmic Framework", Figure 1.
+ * Right-looking blocked LU without pivoting with block size nb.  Per block
+ * step: the diagonal block is factored in FP32; the block column
+ * L21 = A21 U11^-1 and block row U12 = L11^-1 A12 are formed in FP32 by
+ * blocked substitution; both are rounded to the update format `update`
+ * (MXP_F16, MXP_BF16, MXP_F8E4M3 with a power-of-two scale per strip of
+ * rows of L21 / columns of U12; MXP_F32 for an all-FP32 factorisation);
+ * the trailing matrix is updated A22 <- A22 - L21 U12 on the matrix cores
+ * with FP32 accumulation and stored back in `store`.
+ *
+ * On return A holds L (unit lower, strictly below the diagonal; blocks of
+ * L21 stored multiplied by their power-of-two scale) and U (upper) in the
+ * storage format, and `aux` holds what the solve needs: FP32 inverses of
+ * the 64x64 diagonal sub-blocks of every L11 and U11, the per-strip scales
+ * of the stored L21, and the FP64 row scaling.
+ *
+ * Valid (update, store) pairs: (F32,F32), (F16,F16), (BF16,BF16),
+ * (F8E4M3,F16), (F8E4M3,BF16), (F16,F32), (BF16,F32).
+ * nb must be a multiple of 64 in [64, 1024].
+ *
+ * mxp_factor_aux_bytes / mxp_factor_work_bytes give the sizes of `aux`
+ * (kept until the last solve) and `work` (scratch during the call).
+ * `scaling`: MXP_SCALE_NONE, or MXP_SCALE_ROW_EQUIL which first scales
+ * row i of A in place by the power of two nearest 1/diag[i] (diag = the
+ * exact FP64 diagonal from mxp_generate, required then, else may be NULL)
+ * and records the factors in `aux`; the solve applies the same scaling to
+ * its vectors, so X solves the original, unscaled system.
+ * `info` (host pointer, may be NULL): if non-NULL the call synchronises
+ * the stream and stores 0 or the 1-based column of the first zero /
+ * non-finite pivot, returning MXP_ESINGULAR in the latter case; if NULL
+ * the call is asynchronous and a singular pivot is not reported.
+ */
+size_t mxp_factor_aux_bytes(int64_t n, int64_t nb);
+size_t mxp_factor_work_bytes(int64_t n, int64_t nb, int update);
+int mxp_factor(int64_t n, int64_t nb, int update, int store, int scaling, const double *diag, void *A,
+               int64_t lda, void *aux, void *work, size_t work_bytes, int64_t *info, void *stream);
+
+/* per-right-hand-side outcome of the refinement */
+typedef struct {
+    int64_t iters;   /* inner GMRES iterations (matrix-vector products), all restarts */
+    int64_t cycles;  /* restart cycles run */
+    double eta;      /* final HPL scaled residual */
+    int32_t status;  /* MXP_OK, MXP_ENOCONV or MXP_ECRITERION */
+    int32_t pad;
+} mxp_rhs_report;
+
+/*
+ * mxp_solve_ir -- "Algorithmic Framework".
+ * For each right-hand side r: x0 = M^-1 b_r with M^-1 = U^-1 L^-1 S (the
+ * factors from mxp_factor, S the row scaling); then repeat: residual
+ * r = b - A x in FP64 with A regenerated from (seed, diag) instead of read
+ * from memory; eta = ||r||_inf / ((||A||_inf ||x||_inf + ||b||_inf) n 2^-53);
+ * stop when eta < tol; otherwise one cycle of left-preconditioned GMRES
+ * (restart `restart`, modified Gram-Schmidt, Givens rotations, inner stop
+ * when the rotated residual <= tau * ||x||_2) and x += V y.  More than
+ * max_iters inner iterations in total is a failure (MXP_ENOCONV).
+ * All vector work runs in FP64 on the device; only the convergence scalars
+ * cross to the host.
+ *
+ * LU/lda/aux/nb/update/store: as produced by mxp_factor.  seed, diag and
+ * a_inf: as given to / produced by mxp_generate.  B (ldb >= n) is read,
+ * X (ldx >= n) written.  rep: host array of nrhs reports.
+ * restart in [1, 64]; max_iters >= 1; tol > 0 (16 for the HPL test);
+ * tau >= 0 (2^-50 recommended).
+ * Synchronises `stream` (it reads convergence scalars).  Returns MXP_OK
+ * when every right-hand side passed, else the worst positive status.
+ */
+size_t mxp_solve_work_bytes(int64_t n, int64_t nrhs, int restart);
+int mxp_solve_ir(int64_t n, int64_t nb, int update, int store, uint64_t seed, const void *LU, int64_t lda,
+                 const void *aux, const double *diag, const double *a_inf, const double *B, int64_t ldb,
+                 double *X, int64_t ldx, int64_t nrhs, int restart, int max_iters, double tol, double tau,
+                 mxp_rhs_report *rep, void *work, size_t work_bytes, void *stream);
+
+/*
+ * Building blocks exposed for testing and measurement (same conventions;
+ * each has a *_work_bytes query for its scratch buffer).
+ *
+ * mxp_residual: R = B - A X for nrhs columns (R = A X when B is NULL),
+ *   FP64, A regenerated from (seed, diag) -- the refinement's residual
+ *   ("Algorithmic Framework": the 64-bit residual of the refinement).
+ * mxp_apply_prec: Z = M^-1 V = U^-1 L^-1 S V for nrhs columns (nrhs <= 64),
+ *   FP64 arithmetic on the stored factor (the left preconditioner).
+ * mxp_hpl_eta: the HPL scaled residual of one right-hand side (x, b on the
+ *   device) written to the host double *eta; synchronises.
+ */
+size_t mxp_residual_work_bytes(int64_t n, int64_t nrhs);
+int mxp_residual(int64_t n, uint64_t seed, const double *diag, const double *X, int64_t ldx, const double *B,
+                 int64_t ldb, double *R, int64_t ldr, int64_t nrhs, void *work, size_t work_bytes, void *stream);
+size_t mxp_apply_prec_work_bytes(int64_t n, int64_t nrhs);
+int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, const void *LU, int64_t lda, const void *aux,
+                   const double *V, int64_t ldv, double *Z, int64_t ldz, int64_t nrhs, void *work, size_t work_bytes,
+                   void *stream);
+size_t mxp_hpl_eta_work_bytes(int64_t n);
+int mxp_hpl_eta(int64_t n, uint64_t seed, const double *diag, const double *a_inf, const double *x,
+                const double *b, double *eta, void *work, size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MXP_H */

@@ -1,0 +1,239 @@
+"""paper_2509_19618_amd -- MI355X (gfx950) mixed-precision LU + GMRES-IR solver.
+
+A thin ctypes binding over ``libmxp.so`` (C ABI declared in
+``include/mxp.h``).  Every step of the solve runs in the library's HIP
+kernels; this module only marshals arguments.  PyTorch provides device
+memory and the current HIP stream.  There is no CPU fallback: if the
+library has not been built, every call raises.
+
+Matrices are column-major.  A matrix with leading dimension ``lda`` and
+``ncols`` columns is held in a torch tensor of shape ``(ncols, lda)`` whose
+row ``j`` is column ``j``; :func:`as_matrix` returns the ``(rows, cols)``
+view.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmxp.so")
+
+F64, F32, F16, BF16, F8E4M3 = 0, 1, 2, 3, 4
+OK, EINVAL, EWORKSPACE, EHIP, ESINGULAR, ENOCONV, ECRITERION = 0, -1, -2, -3, 1, 2, 3
+SCALE_NONE, SCALE_ROW_EQUIL = 0, 1
+
+_DTYPE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f8": F8E4M3, "e4m3": F8E4M3, "fp8": F8E4M3}
+_TORCH = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16, F64: torch.float64}
+
+
+class MxpError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("libmxp error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _RhsReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int64), ("cycles", ctypes.c_int64), ("eta", ctypes.c_double),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+_lib = None
+
+# (name, restype, argtypes)
+_P, _I64, _U64, _I, _D, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+SIGNATURES = [
+    ("mxp_last_error", ctypes.c_char_p, []),
+    ("mxp_version", ctypes.c_char_p, []),
+    ("mxp_generate", _I, [_I64, _I64, _U64, _I, _P, _I64, _P, _I64, _P, _P, _P]),
+    ("mxp_factor_aux_bytes", _SZ, [_I64, _I64]),
+    ("mxp_factor_work_bytes", _SZ, [_I64, _I64, _I]),
+    ("mxp_factor", _I, [_I64, _I64, _I, _I, _I, _P, _P, _I64, _P, _P, _SZ, _P, _P]),
+    ("mxp_solve_work_bytes", _SZ, [_I64, _I64, _I]),
+    ("mxp_solve_ir", _I, [_I64, _I64, _I, _I, _U64, _P, _I64, _P, _P, _P, _P, _I64, _P, _I64, _I64, _I, _I, _D, _D,
+                          _P, _P, _SZ, _P]),
+    ("mxp_residual_work_bytes", _SZ, [_I64, _I64]),
+    ("mxp_residual", _I, [_I64, _U64, _P, _P, _I64, _P, _I64, _P, _I64, _I64, _P, _SZ, _P]),
+    ("mxp_apply_prec_work_bytes", _SZ, [_I64, _I64]),
+    ("mxp_apply_prec", _I, [_I64, _I64, _I, _I, _P, _I64, _P, _P, _I64, _P, _I64, _I64, _P, _SZ, _P]),
+    ("mxp_hpl_eta_work_bytes", _SZ, [_I64]),
+    ("mxp_hpl_eta", _I, [_I64, _U64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+]
+
+
+def lib():
+    """Load libmxp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmxp.so is not built (run __graft_entry__.build() or "
+                              "python paper_2509_19618_amd/build.py)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in SIGNATURES:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def dtype_code(d) -> int:
+    if isinstance(d, int):
+        return d
+    return _DTYPE[d]
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(code: int, allow_positive: bool = False) -> int:
+    if code < 0 or (code > 0 and not allow_positive):
+        raise MxpError(code, lib().mxp_last_error().decode())
+    return code
+
+
+def _bytes(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def as_matrix(t: torch.Tensor, rows: int) -> torch.Tensor:
+    """(cols, ld) storage -> (rows, cols) view of a column-major matrix."""
+    return t[:, :rows].t()
+
+
+def round_up(a: int, b: int) -> int:
+    return (a + b - 1) // b * b
+
+
+# ------------------------------------------------------------------ problem
+@dataclass
+class Problem:
+    n: int
+    nrhs: int
+    seed: int
+    store: int
+    A: torch.Tensor | None      # (n, lda) storage, column-major matrix
+    lda: int
+    B: torch.Tensor | None      # (nrhs, n) FP64, column-major n x nrhs
+    diag: torch.Tensor          # (n,) FP64
+    a_inf: torch.Tensor         # (1,) FP64
+
+
+def mxp_generate(n: int, nrhs: int, seed: int, store="f16", with_matrix: bool = True, lda: int | None = None,
+                 device="cuda", stream=None) -> Problem:
+    st = dtype_code(store)
+    lda = lda or round_up(n, 128)
+    A = torch.empty((n, lda), dtype=_TORCH[st], device=device) if with_matrix else None
+    B = torch.empty((max(nrhs, 1), n), dtype=torch.float64, device=device)
+    diag = torch.empty(n, dtype=torch.float64, device=device)
+    a_inf = torch.empty(1, dtype=torch.float64, device=device)
+    _check(lib().mxp_generate(n, nrhs, seed, st, _ptr(A), lda, _ptr(B) if nrhs else None, n, _ptr(diag),
+                              _ptr(a_inf), _stream(stream)))
+    return Problem(n, nrhs, seed, st, A, lda, B if nrhs else None, diag, a_inf)
+
+
+# ------------------------------------------------------------------ factor
+@dataclass
+class Factor:
+    n: int
+    nb: int
+    update: int
+    store: int
+    LU: torch.Tensor
+    lda: int
+    aux: torch.Tensor
+    info: int
+    status: int
+
+
+def mxp_factor(prob: Problem, nb: int, update="f16", scaling: int = SCALE_NONE, work: torch.Tensor | None = None,
+               aux: torch.Tensor | None = None, sync_info: bool = True, stream=None) -> Factor:
+    """Factor prob.A in place (A becomes L\\U).  Returns the Factor handle."""
+    up = dtype_code(update)
+    n, dev = prob.n, prob.A.device
+    L = lib()
+    if aux is None:
+        aux = _bytes(L.mxp_factor_aux_bytes(n, nb), dev)
+    wb = L.mxp_factor_work_bytes(n, nb, up)
+    if work is None:
+        work = _bytes(wb, dev)
+    info = ctypes.c_int64(0)
+    st = L.mxp_factor(n, nb, up, prob.store, scaling, _ptr(prob.diag), _ptr(prob.A), prob.lda, _ptr(aux),
+                      _ptr(work), work.numel(), ctypes.byref(info) if sync_info else None, _stream(stream))
+    _check(st, allow_positive=True)
+    return Factor(n, nb, up, prob.store, prob.A, prob.lda, aux, int(info.value), st)
+
+
+# ------------------------------------------------------------------ solve
+@dataclass
+class SolveResult:
+    X: torch.Tensor          # (nrhs, n) FP64
+    iters: list
+    cycles: list
+    eta: list
+    status: list
+    code: int
+
+
+def mxp_solve_ir(prob: Problem, fac: Factor, B: torch.Tensor | None = None, restart: int = 30, max_iters: int = 50,
+                 tol: float = 16.0, tau: float = 2.0 ** -50, work: torch.Tensor | None = None,
+                 X: torch.Tensor | None = None, stream=None) -> SolveResult:
+    B = prob.B if B is None else B
+    nrhs, n = B.shape[0], prob.n
+    L = lib()
+    if work is None:
+        work = _bytes(L.mxp_solve_work_bytes(n, nrhs, restart), B.device)
+    if X is None:
+        X = torch.empty((nrhs, n), dtype=torch.float64, device=B.device)
+    reps = (_RhsReport * nrhs)()
+    code = L.mxp_solve_ir(n, fac.nb, fac.update, fac.store, prob.seed, _ptr(fac.LU), fac.lda, _ptr(fac.aux),
+                          _ptr(prob.diag), _ptr(prob.a_inf), _ptr(B), n, _ptr(X), n, nrhs, restart, max_iters, tol,
+                          tau, reps, _ptr(work), work.numel(), _stream(stream))
+    _check(code, allow_positive=True)
+    return SolveResult(X, [r.iters for r in reps], [r.cycles for r in reps], [r.eta for r in reps],
+                       [r.status for r in reps], code)
+
+
+def mxp_residual(prob: Problem, X: torch.Tensor, B: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    """R = B - A X (or A X when B is None) with A regenerated; X is (nrhs, n)."""
+    nrhs, n = X.shape[0], prob.n
+    L = lib()
+    work = _bytes(L.mxp_residual_work_bytes(n, nrhs), X.device)
+    R = torch.empty((nrhs, n), dtype=torch.float64, device=X.device)
+    _check(L.mxp_residual(n, prob.seed, _ptr(prob.diag), _ptr(X), n, _ptr(B), n, _ptr(R), n, nrhs, _ptr(work),
+                          work.numel(), _stream(stream)))
+    return R
+
+
+def mxp_apply_prec(fac: Factor, V: torch.Tensor, stream=None) -> torch.Tensor:
+    """Z = M^-1 V for V of shape (nrhs, n)."""
+    nrhs, n = V.shape[0], fac.n
+    L = lib()
+    work = _bytes(L.mxp_apply_prec_work_bytes(n, nrhs), V.device)
+    Z = torch.empty_like(V)
+    _check(L.mxp_apply_prec(n, fac.nb, fac.update, fac.store, _ptr(fac.LU), fac.lda, _ptr(fac.aux), _ptr(V), n,
+                            _ptr(Z), n, nrhs, _ptr(work), work.numel(), _stream(stream)))
+    return Z
+
+
+def mxp_hpl_eta(prob: Problem, x: torch.Tensor, b: torch.Tensor, stream=None) -> float:
+    n = prob.n
+    L = lib()
+    work = _bytes(L.mxp_hpl_eta_work_bytes(n), x.device)
+    eta = ctypes.c_double(0.0)
+    _check(L.mxp_hpl_eta(n, prob.seed, _ptr(prob.diag), _ptr(prob.a_inf), _ptr(x), _ptr(b), ctypes.byref(eta),
+                         _ptr(work), work.numel(), _stream(stream)))
+    return float(eta.value)
+
+
+def exported_symbols():
+    return [name for name, _, _ in SIGNATURES]

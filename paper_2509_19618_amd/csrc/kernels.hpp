@@ -1,0 +1,77 @@
+// kernels.hpp -- host-side launchers of the libmxp kernels (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mxp {
+
+// ---- generation / residual (gen.hip)
+hipError_t fill_u64(void* p, int64_t count, uint64_t v, hipStream_t s);
+hipError_t generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void* A, int64_t lda, double* B, int64_t ldb,
+                    double* diag, double* a_inf, hipStream_t s);
+int64_t regen_chunk_cols(int64_t n);
+size_t regen_partial_bytes(int64_t n, int nr);
+hipError_t regen_matvec(int64_t n, uint64_t seed, const double* diag, const double* X, int64_t ldx, int nr,
+                        const double* B, int64_t ldb, double* R, int64_t ldr, double* P, hipStream_t s);
+int eta_blocks(int64_t n);
+hipError_t hpl_eta_dev(int64_t n, const double* r, const double* x, const double* b, const double* a_inf,
+                       double* part, double* eta_out, hipStream_t s);
+
+// ---- factorisation (lu.hip)
+struct FactorPlan {
+    int64_t n, nb, lda;
+    int update, store;
+    void* A;         // the matrix, overwritten by L\U
+    // aux (persistent)
+    float* T;        // nblk x nb x nb: FP32 L11\U11 of every diagonal block
+    float* linv;     // nblk x (nb/64) x 64 x 64: inverses of the unit-lower 64x64 diagonal sub-blocks
+    float* uinv;     // same for U
+    float* lsc;      // nblk x ceil(n/32): power-of-two scale of every stored 32-row strip of L21
+    double* rowscale;  // n
+    // work (scratch)
+    void* Lq;        // Mpad x nb operand (K-major)
+    void* Uq;        // Npad x nb operand (K-major)
+    float* inv_sa;   // Mpad/32
+    float* inv_sb;   // Npad/32
+    unsigned long long* info;  // 1
+};
+
+struct AuxLayout {
+    size_t T, linv, uinv, lsc, rowscale, total;
+};
+struct WorkLayout {
+    size_t Lq, Uq, inv_sa, inv_sb, info, total;
+};
+AuxLayout aux_layout(int64_t n, int64_t nb);
+WorkLayout work_layout(int64_t n, int64_t nb, int update);
+int dtype_bytes(int dt);
+
+hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t s);
+hipError_t factor_run(const FactorPlan& p, hipStream_t s);
+
+// ---- preconditioner and GMRES pieces (solve.hip)
+struct PrecPlan {
+    int64_t n, nb, lda;
+    int store;
+    const void* A;      // L\U in storage format
+    const float* T;     // aux pieces (see FactorPlan)
+    const float* linv;
+    const float* uinv;
+    const float* lsc;
+    const double* rowscale;
+};
+// Z = U^-1 L^-1 S V for nr columns (V may alias Z); W: n x nr scratch (FP64)
+hipError_t prec_apply(const PrecPlan& p, const double* V, int64_t ldv, double* Z, int64_t ldz, int nr, double* W,
+                      hipStream_t s);
+
+hipError_t mgs_step(int64_t n, const double* V, int k, double* w, double* hcol, double* part, hipStream_t s);
+hipError_t norm_normalize(int64_t n, double* w, double* vout, double* hsub, double* part, hipStream_t s);
+hipError_t givens_step(int k, double* H, int ldh, double* cs, double* sn, double* g, const double* xnorm, double tau,
+                       double* flag, hipStream_t s);
+hipError_t lsq_update(int64_t n, int k, const double* H, int ldh, const double* g, double* y, const double* V,
+                      double* x, hipStream_t s);
+hipError_t vec_norm2(int64_t n, const double* x, double* out, double* part, hipStream_t s);
+hipError_t vec_scale_copy(int64_t n, const double* x, const double* beta, double* v, double* g0, hipStream_t s);
+int red_blocks(int64_t n);
+
+}  // namespace mxp

@@ -1,0 +1,69 @@
+"""CPU checks of the C-ABI library: it loads and exports every function that
+include/mxp.h declares, and the size queries and argument checks behave
+(no device work is launched by these calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2509_19618_amd as mxp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "mxp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mxp_\w+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for want in ("mxp_generate", "mxp_factor", "mxp_solve_ir"):
+        assert want in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(mxp.LIB_PATH)
+    missing = [n for n in _declared() if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(mxp.exported_symbols()) == set(_declared())
+
+
+def test_size_queries():
+    L = mxp.lib()
+    n, nb = 32768, 512
+    aux = L.mxp_factor_aux_bytes(n, nb)
+    # FP32 diagonal blocks + two sets of 64x64 inverses dominate
+    assert aux >= n * nb * 4 + 2 * n * 64 * 4
+    w16 = L.mxp_factor_work_bytes(n, nb, mxp.F16)
+    w8 = L.mxp_factor_work_bytes(n, nb, mxp.F8E4M3)
+    assert w16 > w8 > 0
+    assert L.mxp_solve_work_bytes(n, 1, 30) >= n * 31 * 8
+    assert L.mxp_solve_work_bytes(n, 1, 0) == 0
+    assert L.mxp_factor_work_bytes(n, nb, 99) == 0
+
+
+def test_argument_errors_return_einval_without_device_work():
+    L = mxp.lib()
+    # NULL diag / a_inf, bad n: rejected before anything is enqueued
+    assert L.mxp_generate(0, 0, 1, mxp.F16, None, 0, None, 0, None, None, None) == mxp.EINVAL
+    assert L.mxp_generate(16, 0, 1, mxp.F16, None, 16, None, 16, None, None, None) == mxp.EINVAL
+    assert b"mxp_generate" in L.mxp_last_error()
+    # bad (update, store) pair, bad nb
+    fake = ctypes.c_void_p(256)
+    assert L.mxp_factor(64, 64, mxp.F16, mxp.BF16, 0, None, fake, 64, fake, fake, 1 << 30, None, None) == mxp.EINVAL
+    assert L.mxp_factor(64, 96, mxp.F16, mxp.F16, 0, None, fake, 64, fake, fake, 1 << 30, None, None) == mxp.EINVAL
+    assert L.mxp_factor(64, 64, mxp.F8E4M3, mxp.F16, 0, None, fake, 64, fake, fake, 1 << 30, None, None) == mxp.EINVAL
+    # workspace too small
+    assert L.mxp_factor(64, 64, mxp.F16, mxp.F16, 0, None, fake, 64, fake, fake, 16, None, None) == mxp.EWORKSPACE
+    # row equilibration without the diagonal
+    assert L.mxp_factor(64, 64, mxp.F16, mxp.F16, 1, None, fake, 64, fake, fake, 1 << 30, None, None) == mxp.EINVAL
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(mxp, "_lib", None)
+    monkeypatch.setattr(mxp, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        mxp.lib()
