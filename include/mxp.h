@@ -85,8 +85,9 @@ const char *mxp_version(void);
  *            (seed low 32 bits, seed high 32 bits);
  *   A[i,i] = sum over ALL j of |k(i,j) * 2^-32 - 1/2| (computed exactly);
  *   B[i,r] = draw of stream 1 at (i, r) mapped the same way.
- * A is written in the storage format `store` (MXP_F32, MXP_F16, MXP_BF16),
- * each entry rounded to nearest even from its exact value; lda >= n.
+ * A is written in the storage format `store` (MXP_F32, MXP_F16, MXP_BF16, or
+ * MXP_F64 for an exact copy), each entry rounded to nearest even from its
+ * exact value; lda >= n.
  * A may be NULL (nothing stored: the solver regenerates A on the fly).
  * B (FP64, ldb >= n) may be NULL when nrhs == 0.
  * diag (FP64, n entries): the exact diagonal; required.
@@ -189,9 +190,34 @@ size_t mxp_apply_prec_work_bytes(int64_t n, int64_t nrhs);
 int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, const void *LU, int64_t lda, const void *aux,
                    const double *V, int64_t ldv, double *Z, int64_t ldz, int64_t nrhs, void *work, size_t work_bytes,
                    void *stream);
+/*
+ * mxp_trailing_update: the Schur-complement update of one block step
+ * ("Algorithmic Framework", Figure 1), C <- C - diag(inv_sa) Aq Bq^T diag(inv_sb):
+ * C is M x N column-major in the storage format (ldc >= M); Aq (M x K) and
+ * Bq (N x K) are the operands in the update format, each row's K values
+ * contiguous, with the row counts padded to a multiple of 256 (padding rows
+ * are read, never written); inv_sa / inv_sb hold one FP32 factor per 32 rows
+ * of Aq / Bq (padded likewise).  K * element size must be a multiple of 128
+ * bytes.  Asynchronous.
+ */
+int mxp_trailing_update(int64_t M, int64_t N, int64_t K, int update, int store, void *C, int64_t ldc,
+                        const void *Aq, const void *Bq, const float *inv_sa, const float *inv_sb, void *stream);
 size_t mxp_hpl_eta_work_bytes(int64_t n);
 int mxp_hpl_eta(int64_t n, uint64_t seed, const double *diag, const double *a_inf, const double *x,
                 const double *b, double *eta, void *work, size_t work_bytes, void *stream);
+
+/*
+ * Timing of kernel classes with HIP events recorded on the stream each
+ * kernel is launched on (off by default).  Classes: 0 trailing update,
+ * 1 strip TRSMs, 2 diagonal-block LU, 3 preconditioner apply, 4 regenerating
+ * residual / matrix-vector product.  mxp_profile_read synchronises on the
+ * recorded events and returns, for one class, the summed kernel time, the
+ * summed algorithmic flops and bytes, and the number of timed launches
+ * since the last reset.
+ */
+int mxp_profile_enable(int on);
+int mxp_profile_reset(void);
+int mxp_profile_read(int cls, double *total_ms, double *flops, double *bytes, int64_t *launches);
 
 #ifdef __cplusplus
 }

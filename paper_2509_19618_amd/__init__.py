@@ -61,7 +61,13 @@ SIGNATURES = [
     ("mxp_apply_prec", _I, [_I64, _I64, _I, _I, _P, _I64, _P, _P, _I64, _P, _I64, _I64, _P, _SZ, _P]),
     ("mxp_hpl_eta_work_bytes", _SZ, [_I64]),
     ("mxp_hpl_eta", _I, [_I64, _U64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    ("mxp_trailing_update", _I, [_I64, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P]),
+    ("mxp_profile_enable", _I, [_I]),
+    ("mxp_profile_reset", _I, []),
+    ("mxp_profile_read", _I, [_I, _P, _P, _P, _P]),
 ]
+
+PROF_GEMM, PROF_TRSM, PROF_DIAG, PROF_PREC, PROF_REGEN = 0, 1, 2, 3, 4
 
 
 def lib():
@@ -235,5 +241,27 @@ def mxp_hpl_eta(prob: Problem, x: torch.Tensor, b: torch.Tensor, stream=None) ->
     return float(eta.value)
 
 
+def mxp_trailing_update(C: torch.Tensor, ldc: int, M: int, N: int, K: int, update, store, Aq: torch.Tensor,
+                        Bq: torch.Tensor, inv_sa: torch.Tensor, inv_sb: torch.Tensor, stream=None) -> None:
+    """C <- C - diag(inv_sa) Aq Bq^T diag(inv_sb) (see include/mxp.h)."""
+    _check(lib().mxp_trailing_update(M, N, K, dtype_code(update), dtype_code(store), _ptr(C), ldc, _ptr(Aq),
+                                     _ptr(Bq), _ptr(inv_sa), _ptr(inv_sb), _stream(stream)))
+
+
 def exported_symbols():
     return [name for name, _, _ in SIGNATURES]
+
+
+def profile_enable(on: bool = True) -> None:
+    _check(lib().mxp_profile_enable(1 if on else 0))
+
+
+def profile_reset() -> None:
+    _check(lib().mxp_profile_reset())
+
+
+def profile_read(cls: int) -> dict:
+    """Summed event time (ms), algorithmic flops and bytes, launches of a kernel class."""
+    ms, fl, by, cnt = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+    _check(lib().mxp_profile_read(cls, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by), ctypes.byref(cnt)))
+    return {"ms": ms.value, "flops": fl.value, "bytes": by.value, "launches": cnt.value}

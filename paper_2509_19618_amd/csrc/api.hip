@@ -8,6 +8,7 @@
 #include "../../include/mxp.h"
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 using namespace mxp;
 
@@ -30,7 +31,7 @@ static int set_err(int code, const char* fmt, const char* what) {
 extern "C" const char* mxp_last_error(void) { return g_err; }
 extern "C" const char* mxp_version(void) { return "libmxp 0.1 (gfx950)"; }
 
-static bool valid_store(int st) { return st == MXP_F32 || st == MXP_F16 || st == MXP_BF16; }
+static bool valid_store(int st) { return st == MXP_F64 || st == MXP_F32 || st == MXP_F16 || st == MXP_BF16; }
 static bool valid_pair(int update, int store) {
     return (update == MXP_F32 && store == MXP_F32) || (update == MXP_F16 && store == MXP_F16) ||
            (update == MXP_BF16 && store == MXP_BF16) || (update == MXP_F8E4M3 && store == MXP_F16) ||
@@ -76,6 +77,8 @@ static FactorPlan make_plan(int64_t n, int64_t nb, int update, int store, void* 
     p.uinv = (float*)(a + al.uinv);
     p.lsc = (float*)(a + al.lsc);
     p.rowscale = (double*)(a + al.rowscale);
+    p.linv_full = (float*)(a + al.linv_full);
+    p.uinv_full = (float*)(a + al.uinv_full);
     if (work) {
         WorkLayout wl = work_layout(n, nb, update);
         char* w = (char*)work;
@@ -139,7 +142,7 @@ static SolveLayout solve_layout(int64_t n, int64_t nrhs, int restart) {
     L.r = off; off = al256(off + (size_t)n * 8);
     L.z = off; off = al256(off + (size_t)n * 8);
     L.P = off; off = al256(off + regen_partial_bytes(n, 8 < nrhs ? 8 : (int)std::max<int64_t>(nrhs, 1)));
-    L.W = off; off = al256(off + (size_t)n * std::max<int64_t>(nrhs, 1) * 8);
+    L.W = off; off = al256(off + 2 * (size_t)n * std::max<int64_t>(nrhs, 1) * 8);
     L.part = off; off = al256(off + 2 * 256 * 8);
     L.epart = off; off = al256(off + 3 * 512 * 8);
     L.H = off; off = al256(off + (size_t)(m + 1) * m * 8);
@@ -162,6 +165,7 @@ static PrecPlan make_prec(int64_t n, int64_t nb, int store, const void* LU, int6
     PrecPlan p;
     p.n = n; p.nb = nb; p.lda = lda; p.store = store; p.A = LU;
     p.T = f.T; p.linv = f.linv; p.uinv = f.uinv; p.lsc = f.lsc; p.rowscale = f.rowscale;
+    p.linv_full = f.linv_full; p.uinv_full = f.uinv_full;
     return p;
 }
 
@@ -266,7 +270,7 @@ extern "C" int mxp_residual(int64_t n, uint64_t seed, const double* diag, const 
 
 extern "C" size_t mxp_apply_prec_work_bytes(int64_t n, int64_t nrhs) {
     if (n < 1 || nrhs < 1) return 0;
-    return (size_t)n * nrhs * 8;
+    return 2 * (size_t)n * nrhs * 8;
 }
 
 extern "C" int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, const void* LU, int64_t lda,
@@ -302,5 +306,18 @@ extern "C" int mxp_hpl_eta(int64_t n, uint64_t seed, const double* diag, const d
     HIPCHK(hpl_eta_dev(n, r, x, b, a_inf, ep, out, s));
     HIPCHK(hipMemcpyAsync(eta, out, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    return MXP_OK;
+}
+
+extern "C" int mxp_trailing_update(int64_t M, int64_t N, int64_t K, int update, int store, void* C, int64_t ldc,
+                                   const void* Aq, const void* Bq, const float* inv_sa, const float* inv_sb,
+                                   void* stream) {
+    if (M < 0 || N < 0 || K < 1 || K > 4096 || ldc < (M > 1 ? M : 1) || !valid_pair(update, store) ||
+        (K * dtype_bytes(update)) % 128 || (M > 0 && N > 0 && (!C || !Aq || !Bq || !inv_sa || !inv_sb)))
+        return set_err(MXP_EINVAL, "mxp_trailing_update: bad argument%s", "");
+    prof::begin((hipStream_t)stream);
+    HIPCHK(gemm_update(update, store, C, ldc, M, N, (int)K, Aq, Bq, inv_sa, inv_sb, (hipStream_t)stream));
+    prof::end(prof::GEMM, (hipStream_t)stream, 2.0 * M * (double)N * K,
+              2.0 * M * (double)N * dtype_bytes(store) + (double)(M + N) * K * dtype_bytes(update));
     return MXP_OK;
 }

@@ -156,6 +156,14 @@ MXP_DEV float e4m3_bits_to_f32(uint8_t b) {
 
 // storage loads / stores -----------------------------------------------------
 template <int ST> struct Store;
+template <> struct Store<F64> {
+    typedef double T;
+    static MXP_DEV float load(const T* p, int64_t i) { return (float)p[i]; }
+    static MXP_DEV T from_f64(double d) { return d; }
+    static MXP_DEV T from_f32(float f) { return f; }
+    static constexpr int scale_exp = 0;
+    static constexpr bool scaled = false;
+};
 template <> struct Store<F32> {
     typedef float T;
     static MXP_DEV float load(const T* p, int64_t i) { return p[i]; }

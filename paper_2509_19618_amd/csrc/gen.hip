@@ -4,6 +4,7 @@
 // Framework", 64-bit residual of the refinement and the HPL scaled residual).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace mxp {
 
@@ -121,6 +122,7 @@ static hipError_t gen_launch(int64_t n, int64_t nrhs, uint64_t seed, void* A, in
 hipError_t generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void* A, int64_t lda, double* B, int64_t ldb,
                     double* diag, double* a_inf, hipStream_t s) {
     switch (store) {
+    case F64: return gen_launch<F64>(n, nrhs, seed, A, lda, B, ldb, diag, a_inf, s);
     case F32: return gen_launch<F32>(n, nrhs, seed, A, lda, B, ldb, diag, a_inf, s);
     case F16: return gen_launch<F16>(n, nrhs, seed, A, lda, B, ldb, diag, a_inf, s);
     case BF16: return gen_launch<BF16>(n, nrhs, seed, A, lda, B, ldb, diag, a_inf, s);
@@ -201,11 +203,10 @@ hipError_t regen_matvec(int64_t n, uint64_t seed, const double* diag, const doub
     int64_t nchunk = (n + cc - 1) / cc;
     dim3 g((unsigned)((n + 255) / 256), (unsigned)nchunk);
     // the column loop steps by 4 from a chunk start that is a multiple of 4
+    prof::begin(s);
     for (int r0 = 0; r0 < nr;) {
         int left = nr - r0;
         int w = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
-        double* Pr = P + (int64_t)r0 * 0;  // partials are laid out per call below
-        (void)Pr;
         switch (w) {
         case 8: k_regen_gemv<8><<<g, dim3(256), 0, s>>>(n, seed, X + r0 * ldx, ldx, P, cc); break;
         case 4: k_regen_gemv<4><<<g, dim3(256), 0, s>>>(n, seed, X + r0 * ldx, ldx, P, cc); break;
@@ -219,6 +220,7 @@ hipError_t regen_matvec(int64_t n, uint64_t seed, const double* diag, const doub
         if ((e = hipGetLastError())) return e;
         r0 += w;
     }
+    prof::end(prof::REGEN, s, 2.0 * n * (double)n * nr, 16.0 * n * nr + 8.0 * n * nchunk * nr);
     return hipSuccess;
 }
 

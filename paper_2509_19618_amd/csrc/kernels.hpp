@@ -28,6 +28,8 @@ struct FactorPlan {
     float* uinv;     // same for U
     float* lsc;      // nblk x ceil(n/32): power-of-two scale of every stored 32-row strip of L21
     double* rowscale;  // n
+    float* linv_full;  // nblk x nb x nb: L11^-1 of every diagonal block (FP32, ld nb)
+    float* uinv_full;  // nblk x nb x nb: U11^-1
     // work (scratch)
     void* Lq;        // Mpad x nb operand (K-major)
     void* Uq;        // Npad x nb operand (K-major)
@@ -37,7 +39,7 @@ struct FactorPlan {
 };
 
 struct AuxLayout {
-    size_t T, linv, uinv, lsc, rowscale, total;
+    size_t T, linv, uinv, lsc, rowscale, linv_full, uinv_full, total;
 };
 struct WorkLayout {
     size_t Lq, Uq, inv_sa, inv_sb, info, total;
@@ -46,6 +48,9 @@ AuxLayout aux_layout(int64_t n, int64_t nb);
 WorkLayout work_layout(int64_t n, int64_t nb, int update);
 int dtype_bytes(int dt);
 
+// C (M x N, storage) <- C - diag(inv_sa) Aq Bq^T diag(inv_sb); Aq/Bq rows padded to 256
+hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq,
+                       const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s);
 hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t s);
 hipError_t factor_run(const FactorPlan& p, hipStream_t s);
 
@@ -59,8 +64,10 @@ struct PrecPlan {
     const float* uinv;
     const float* lsc;
     const double* rowscale;
+    const float* linv_full;
+    const float* uinv_full;
 };
-// Z = U^-1 L^-1 S V for nr columns (V may alias Z); W: n x nr scratch (FP64)
+// Z = U^-1 L^-1 S V for nr columns (V may alias Z); W: 2 x n x nr scratch (FP64)
 hipError_t prec_apply(const PrecPlan& p, const double* V, int64_t ldv, double* Z, int64_t ldz, int nr, double* W,
                       hipStream_t s);
 

@@ -14,6 +14,7 @@
 //      result rounded to the storage format.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace mxp {
 
@@ -39,6 +40,8 @@ AuxLayout aux_layout(int64_t n, int64_t nb) {
     L.uinv = off; off = al256(off + (size_t)nblk * nb * 64 * 4);
     L.lsc = off; off = al256(off + (size_t)nblk * ((n + 31) / 32) * 4);
     L.rowscale = off; off = al256(off + (size_t)n * 8);
+    L.linv_full = off; off = al256(off + (size_t)nblk * nb * nb * 4);
+    L.uinv_full = off; off = al256(off + (size_t)nblk * nb * nb * 4);
     L.total = off;
     return L;
 }
@@ -120,51 +123,52 @@ __global__ __launch_bounds__(256) void k_diag_store(typename Store<ST>::T* A, in
 }
 
 // LU of the 64x64 tile T[s:s+64, s:s+64] in LDS, then the inverses of its
-// unit-lower and upper factors by column sweeps.  A zero or non-finite
-// pivot records its 1-based global column in *info (atomic min).
+// unit-lower and upper factors by column sweeps.  Thread (r, g): row r,
+// columns g, g+4, ...  A zero or non-finite pivot records its 1-based
+// global column in *info (atomic min).
 __global__ __launch_bounds__(256) void k_leaf_lu(float* T, int ldt, int s, float* linv, float* uinv,
                                                  unsigned long long* info, int64_t col0) {
     __shared__ float a[64][65];
     __shared__ float xl[64][65];
     __shared__ float xu[64][65];
-    int tid = threadIdx.x;
-    for (int e = tid; e < 4096; e += 256) {
-        int i = e & 63, j = e >> 6;
-        a[i][j] = T[(s + i) + (int64_t)(s + j) * ldt];
-        xl[i][j] = (i == j) ? 1.0f : 0.0f;
-        xu[i][j] = (i == j) ? 1.0f : 0.0f;
+    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+    for (int c = g; c < 64; c += 4) {
+        a[r][c] = T[(s + r) + (int64_t)(s + c) * ldt];
+        xl[r][c] = (r == c) ? 1.0f : 0.0f;
+        xu[r][c] = (r == c) ? 1.0f : 0.0f;
     }
     __syncthreads();
     for (int j = 0; j < 64; ++j) {
-        float p = a[j][j];
+        const float p = a[j][j];
         if (tid == 0 && (p == 0.0f || !isfinite(p))) atomicMin(info, (unsigned long long)(col0 + s + j + 1));
-        if (tid > j && tid < 64) a[tid][j] = a[tid][j] / p;
+        if (g == 0 && r > j) a[r][j] = a[r][j] / p;
         __syncthreads();
-        int w = 63 - j;  // trailing size
-        for (int e = tid; e < w * w; e += 256) {
-            int i = j + 1 + e % w, c = j + 1 + e / w;
-            a[i][c] -= a[i][j] * a[j][c];
+        if (r > j) {
+            const float l = a[r][j];
+            for (int c = j + 1 + g; c < 64; c += 4) a[r][c] -= l * a[j][c];
         }
         __syncthreads();
     }
-    // inverse of unit-lower L: X = I; for t: rows i > t: X[i][:t+1] -= L[i][t] X[t][:t+1]
-    // inverse of U: X = I; for t from 63 down: X[t][:] /= U[t][t]; rows i < t: X[i][:] -= U[i][t] X[t][:]
+    // L^-1: X = I; for t ascending, rows i > t: X[i][0:t] -= L[i][t] X[t][0:t]
+    // U^-1: X = I; for t descending: X[t][:] /= U[t][t]; rows i < t: X[i][t:] -= U[i][t] X[t][t:]
     for (int t = 0; t < 64; ++t) {
-        int tu = 63 - t;
-        if (tid < 64) xu[tu][tid] = xu[tu][tid] / a[tu][tu];
+        const int tu = 63 - t;
+        if (g == 0) xu[tu][r] = xu[tu][r] / a[tu][tu];
         __syncthreads();
-        for (int e = tid; e < 64 * 64; e += 256) {
-            int i = e >> 6, c = e & 63;
-            if (i > t && c <= t) xl[i][c] -= a[i][t] * xl[t][c];
-            if (i < tu && c >= tu) xu[i][c] -= a[i][tu] * xu[tu][c];
+        if (r > t) {
+            const float l = a[r][t];
+            for (int c = g; c <= t; c += 4) xl[r][c] -= l * xl[t][c];
+        }
+        if (r < tu) {
+            const float u = a[r][tu];
+            for (int c = tu + g; c < 64; c += 4) xu[r][c] -= u * xu[tu][c];
         }
         __syncthreads();
     }
-    for (int e = tid; e < 4096; e += 256) {
-        int i = e & 63, j = e >> 6;
-        T[(s + i) + (int64_t)(s + j) * ldt] = a[i][j];
-        linv[i + 64 * j] = xl[i][j];
-        uinv[i + 64 * j] = xu[i][j];
+    for (int c = g; c < 64; c += 4) {
+        T[(s + r) + (int64_t)(s + c) * ldt] = a[r][c];
+        linv[r + 64 * c] = xl[r][c];
+        uinv[r + 64 * c] = xu[r][c];
     }
 }
 
@@ -237,32 +241,13 @@ __global__ __launch_bounds__(256) void k_inner_update(float* T, int ldt, int s, 
 // ============================================================== strip TRSMs + rounding
 constexpr int SR = 32;  // rows (columns) per strip of L21 (U12) and per scale
 
-// L21 strip: X (32 x nb) = A21[rows, :] U11^-1 by blocked substitution over
-// 64-column blocks, X_J = (A_J - sum_{I<J} X_I U_IJ) Uinv_J; then
-// amax -> power-of-two scales; writes the operand Lq (K-major, update
-// format, scaled), the stored L21 (storage format, scaled) and the scales.
-template <int ST, int OP>
-__global__ __launch_bounds__(256) void k_trsm_L(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
-                                                const float* __restrict__ T, const float* __restrict__ uinv,
-                                                typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk) {
-    extern __shared__ float smem[];
-    const int SP = nb + 4;                  // row pitch of the strip
-    float* S = smem;                        // [SR][SP]
-    float (*sU)[65] = (float (*)[65])(smem + SR * SP);
-    int tid = threadIdx.x;
-    int w = blockIdx.x;
-    int64_t r0 = k + nb + (int64_t)SR * w;  // first global row of the strip
-    int64_t rv = n - r0;                    // valid rows
-    if (rv > SR) rv = SR;
-    if (rv < 0) rv = 0;
-    // load (rows beyond n are zero)
-    for (int e = tid; e < SR * nb; e += 256) {
-        int ii = e % SR, c = e / SR;
-        S[ii * SP + c] = (ii < rv) ? Store<ST>::load(A, (r0 + ii) + (k + c) * lda) : 0.0f;
-    }
-    __syncthreads();
+// Blocked substitution on a 32-row strip held in LDS (row pitch SP):
+// X_J <- (X_J - sum_{I<J} X_I U_IJ) Uinv_J for the nbk 64-column blocks J,
+// with U_IJ read from T (FP32, ld ldt) and Uinv_J the 64x64 inverses.
+__device__ void strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ldt,
+                                  const float* __restrict__ uinv, float (*sU)[65]) {
+    const int tid = threadIdx.x;
     const int cc = tid & 63, rb = (tid >> 6) * 8;  // this thread: column cc, rows rb..rb+7
-    const int nbk = nb / 64;
     for (int J = 0; J < nbk; ++J) {
         float acc[8];
 #pragma unroll
@@ -270,7 +255,7 @@ __global__ __launch_bounds__(256) void k_trsm_L(typename Store<ST>::T* A, int64_
         for (int I = 0; I < J; ++I) {
             for (int e = tid; e < 4096; e += 256) {
                 int i = e & 63, j = e >> 6;
-                sU[i][j] = T[(I * 64 + i) + (int64_t)(J * 64 + j) * nb];
+                sU[i][j] = T[(I * 64 + i) + (int64_t)(J * 64 + j) * ldt];
             }
             __syncthreads();
             for (int kk = 0; kk < 64; ++kk) {
@@ -298,56 +283,14 @@ __global__ __launch_bounds__(256) void k_trsm_L(typename Store<ST>::T* A, int64_
         for (int r = 0; r < 8; ++r) S[(rb + r) * SP + J * 64 + cc] = y[r];
         __syncthreads();
     }
-    // amax of the strip
-    __shared__ float red[4];
-    float m = 0.0f;
-    for (int e = tid; e < SR * nb; e += 256) m = fmaxf(m, fabsf(S[(e / nb) * SP + (e % nb)]));
-    m = warp_maxf(m);
-    if ((tid & 63) == 0) red[tid >> 6] = m;
-    __syncthreads();
-    float amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    float s_op = Operand<OP>::scaled ? pow2_scale(amax, Operand<OP>::scale_exp) : 1.0f;
-    float s_st = Store<ST>::scaled ? pow2_scale(amax, Store<ST>::scale_exp) : 1.0f;
-    if (tid == 0) {
-        inv_sa[w] = 1.0f / s_op;
-        if (rv > 0) lsc_blk[r0 / SR] = s_st;
-    }
-    // operand, K-major: row (SR*w + ii) holds nb contiguous values
-    for (int e = tid; e < SR * nb; e += 256) {
-        int ii = e / nb, c = e % nb;
-        Lq[((int64_t)SR * w + ii) * nb + c] = Operand<OP>::from_f32(S[ii * SP + c] * s_op);
-    }
-    // stored L21 (column-major, scaled)
-    for (int e = tid; e < SR * nb; e += 256) {
-        int ii = e % SR, c = e / SR;
-        if (ii < rv) A[(r0 + ii) + (k + c) * lda] = Store<ST>::from_f32(S[ii * SP + c] * s_st);
-    }
 }
 
-// U12 strip: Y (nb x 32) = L11^-1 A12[:, cols] by blocked substitution over
-// 64-row blocks, Y_I = Linv_I (A_I - sum_{J<I} L_IJ Y_J); operand Uq
-// (K-major: column j has nb contiguous values) scaled, stored U12 unscaled.
-template <int ST, int OP>
-__global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
-                                                const float* __restrict__ T, const float* __restrict__ linv,
-                                                typename Operand<OP>::T* Uq, float* inv_sb) {
-    extern __shared__ float smem[];
-    const int SP = nb + 4;
-    float* S = smem;                        // [SR cols][SP]: S[cc*SP + kk]
-    float (*sL)[65] = (float (*)[65])(smem + SR * SP);
-    int tid = threadIdx.x;
-    int w = blockIdx.x;
-    int64_t c0 = k + nb + (int64_t)SR * w;
-    int64_t cv = n - c0;
-    if (cv > SR) cv = SR;
-    if (cv < 0) cv = 0;
-    for (int e = tid; e < SR * nb; e += 256) {
-        int kk = e % nb, cc = e / nb;
-        S[cc * SP + kk] = (cc < cv) ? Store<ST>::load(A, (k + kk) + (c0 + cc) * lda) : 0.0f;
-    }
-    __syncthreads();
+// Blocked substitution on a 32-column strip held in LDS as S[col * SP + row]:
+// Y_I <- Linv_I (Y_I - sum_{J<I} L_IJ Y_J) for the nbk 64-row blocks I.
+__device__ void strip_left_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ldt,
+                                 const float* __restrict__ linv, float (*sL)[65]) {
+    const int tid = threadIdx.x;
     const int kr = tid & 63, cb = (tid >> 6) * 8;  // row kr of the 64-block, columns cb..cb+7
-    const int nbk = nb / 64;
     for (int I = 0; I < nbk; ++I) {
         float acc[8];
 #pragma unroll
@@ -355,7 +298,7 @@ __global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_
         for (int J = 0; J < I; ++J) {
             for (int e = tid; e < 4096; e += 256) {
                 int i = e >> 6, j = e & 63;
-                sL[i][j] = T[(I * 64 + i) + (int64_t)(J * 64 + j) * nb];
+                sL[i][j] = T[(I * 64 + i) + (int64_t)(J * 64 + j) * ldt];
             }
             __syncthreads();
             for (int t = 0; t < 64; ++t) {
@@ -383,14 +326,81 @@ __global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_
         for (int r = 0; r < 8; ++r) S[(cb + r) * SP + I * 64 + kr] = y[r];
         __syncthreads();
     }
+}
+
+__device__ float strip_amax(const float* S, int SP, int width) {
     __shared__ float red[4];
+    const int tid = threadIdx.x;
     float m = 0.0f;
-    for (int e = tid; e < SR * nb; e += 256) m = fmaxf(m, fabsf(S[(e / nb) * SP + (e % nb)]));
+    for (int e = tid; e < SR * width; e += 256) m = fmaxf(m, fabsf(S[(e / width) * SP + (e % width)]));
     m = warp_maxf(m);
     if ((tid & 63) == 0) red[tid >> 6] = m;
     __syncthreads();
     float amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    float s_op = Operand<OP>::scaled ? pow2_scale(amax, Operand<OP>::scale_exp) : 1.0f;
+    __syncthreads();
+    return amax;
+}
+
+// L21 strip: X (32 x nb) = A21[rows, :] U11^-1, then amax -> power-of-two
+// scales; writes the operand Lq (K-major, update format, scaled), the stored
+// L21 (storage format, scaled) and the scales.
+template <int ST, int OP>
+__global__ __launch_bounds__(256) void k_trsm_L(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
+                                                const float* __restrict__ T, const float* __restrict__ uinv,
+                                                typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk) {
+    extern __shared__ float smem[];
+    const int SP = nb + 4;
+    float* S = smem;
+    float (*sU)[65] = (float (*)[65])(smem + SR * SP);
+    const int tid = threadIdx.x, w = blockIdx.x;
+    const int64_t r0 = k + nb + (int64_t)SR * w;
+    int64_t rv = n - r0;
+    rv = rv > SR ? SR : (rv < 0 ? 0 : rv);
+    for (int e = tid; e < SR * nb; e += 256) {
+        int ii = e % SR, c = e / SR;
+        S[ii * SP + c] = (ii < rv) ? Store<ST>::load(A, (r0 + ii) + (k + c) * lda) : 0.0f;
+    }
+    __syncthreads();
+    strip_right_solve(S, SP, nb / 64, T, nb, uinv, sU);
+    const float amax = strip_amax(S, SP, nb);
+    const float s_op = Operand<OP>::scaled ? pow2_scale(amax, Operand<OP>::scale_exp) : 1.0f;
+    const float s_st = Store<ST>::scaled ? pow2_scale(amax, Store<ST>::scale_exp) : 1.0f;
+    if (tid == 0) {
+        inv_sa[w] = 1.0f / s_op;
+        if (rv > 0) lsc_blk[r0 / SR] = s_st;
+    }
+    for (int e = tid; e < SR * nb; e += 256) {
+        int ii = e / nb, c = e % nb;
+        Lq[((int64_t)SR * w + ii) * nb + c] = Operand<OP>::from_f32(S[ii * SP + c] * s_op);
+    }
+    for (int e = tid; e < SR * nb; e += 256) {
+        int ii = e % SR, c = e / SR;
+        if (ii < rv) A[(r0 + ii) + (k + c) * lda] = Store<ST>::from_f32(S[ii * SP + c] * s_st);
+    }
+}
+
+// U12 strip: Y (nb x 32) = L11^-1 A12[:, cols]; operand Uq (K-major: column
+// j has nb contiguous values) scaled, stored U12 unscaled.
+template <int ST, int OP>
+__global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
+                                                const float* __restrict__ T, const float* __restrict__ linv,
+                                                typename Operand<OP>::T* Uq, float* inv_sb) {
+    extern __shared__ float smem[];
+    const int SP = nb + 4;
+    float* S = smem;
+    float (*sL)[65] = (float (*)[65])(smem + SR * SP);
+    const int tid = threadIdx.x, w = blockIdx.x;
+    const int64_t c0 = k + nb + (int64_t)SR * w;
+    int64_t cv = n - c0;
+    cv = cv > SR ? SR : (cv < 0 ? 0 : cv);
+    for (int e = tid; e < SR * nb; e += 256) {
+        int kk = e % nb, cc = e / nb;
+        S[cc * SP + kk] = (cc < cv) ? Store<ST>::load(A, (k + kk) + (c0 + cc) * lda) : 0.0f;
+    }
+    __syncthreads();
+    strip_left_solve(S, SP, nb / 64, T, nb, linv, sL);
+    const float amax = strip_amax(S, SP, nb);
+    const float s_op = Operand<OP>::scaled ? pow2_scale(amax, Operand<OP>::scale_exp) : 1.0f;
     if (tid == 0) inv_sb[w] = 1.0f / s_op;
     for (int e = tid; e < SR * nb; e += 256) {
         int cc = e / nb, kk = e % nb;
@@ -399,150 +409,56 @@ __global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_
     }
 }
 
-// ============================================================== trailing update (MFMA)
-// C (M x N, storage format, column-major) -= diag(inv_sa) (Lq Uq^T) diag(inv_sb)
-// Lq: M x K (K-major), Uq: N x K (K-major), K = nb.
-// Tile 256 x 256, 512 threads = 8 waves in a 2 (M) x 4 (N) grid, each wave
-// 128 x 64 = 4 x 2 MFMA 32x32 blocks.  K advances 128 bytes per stage
-// through two LDS buffers; a lane's fragment for one MFMA is a contiguous
-// run of the K-major row.
-typedef _Float16 h8v __attribute__((ext_vector_type(8)));
-typedef __bf16 b8v __attribute__((ext_vector_type(8)));
-typedef float f16v __attribute__((ext_vector_type(16)));
-typedef int i8v __attribute__((ext_vector_type(8)));
-typedef int i4v __attribute__((ext_vector_type(4)));
-
-template <int OP> struct Mfma;
-template <> struct Mfma<F16> {
-    static constexpr int KB = 32;  // bytes of a row consumed per instruction (16 halves)
-    static MXP_DEV f16v run(const char* a, const char* b, f16v c) {
-        h8v x = *(const h8v*)a, y = *(const h8v*)b;
-        return __builtin_amdgcn_mfma_f32_32x32x16_f16(x, y, c, 0, 0, 0);
+// Full inverses of the diagonal blocks (for the preconditioner), all blocks
+// in one launch: blockIdx.y = block, blockIdx.x = 32-wide strip.
+// U11^-1 rows r0..r0+31 = I[r0:r0+32, :] U11^-1; L11^-1 columns = L11^-1 I[:, c0:c0+32].
+__global__ __launch_bounds__(256) void k_inv_upper(int64_t n, int nb, const float* __restrict__ Tall,
+                                                   const float* __restrict__ uinv_all, float* __restrict__ out_all) {
+    extern __shared__ float smem[];
+    const int64_t blk = blockIdx.y;
+    const int64_t k = blk * nb;
+    const int kb = (int)(n - k < nb ? n - k : nb);
+    const int kbp = (kb + 63) / 64 * 64;
+    const int r0 = SR * blockIdx.x;
+    if (r0 >= kbp) return;
+    const int SP = kbp + 4;
+    float* S = smem;
+    float (*sU)[65] = (float (*)[65])(smem + SR * SP);
+    for (int e = threadIdx.x; e < SR * kbp; e += 256) {
+        int ii = e % SR, c = e / SR;
+        S[ii * SP + c] = (r0 + ii == c) ? 1.0f : 0.0f;
     }
-};
-template <> struct Mfma<BF16> {
-    static constexpr int KB = 32;
-    static MXP_DEV f16v run(const char* a, const char* b, f16v c) {
-        b8v x = *(const b8v*)a, y = *(const b8v*)b;
-        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(x, y, c, 0, 0, 0);
-    }
-};
-template <> struct Mfma<F8> {
-    static constexpr int KB = 64;  // 64 fp8 values
-    static MXP_DEV f16v run(const char* a, const char* b, f16v c) {
-        i4v a0 = *(const i4v*)a, a1 = *(const i4v*)(a + 16);
-        i4v b0 = *(const i4v*)b, b1 = *(const i4v*)(b + 16);
-        i8v x = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
-        i8v y = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
-        // formats 0/0 = fp8 e4m3 for both operands; E8M0 scales of 1.0
-        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(x, y, c, 0, 0, 0, 0x7f7f7f7f, 0, 0x7f7f7f7f);
-    }
-};
-template <> struct Mfma<F32> {
-    static constexpr int KB = 8;   // 2 floats
-    static MXP_DEV f16v run(const char* a, const char* b, f16v c) {
-        return __builtin_amdgcn_mfma_f32_32x32x2f32(*(const float*)a, *(const float*)b, c, 0, 0, 0);
-    }
-};
-
-constexpr int GT = 256;           // tile edge
-constexpr int GBK = 128;          // K bytes per stage
-constexpr int GPITCH = GBK + 16;  // LDS row pitch in bytes (conflict-free 16-byte reads)
-constexpr int GSTAGE = GT * GPITCH;
-
-template <int OP, int ST>
-__global__ __launch_bounds__(512) void k_gemm_update(typename Store<ST>::T* C, int64_t ldc, int64_t M, int64_t N,
-                                                     int K, const char* __restrict__ Aq, const char* __restrict__ Bq,
-                                                     const float* __restrict__ inv_sa,
-                                                     const float* __restrict__ inv_sb, int tiles_m) {
-    extern __shared__ __attribute__((aligned(16))) char lds[];
-    char* sA = lds;                  // [2][GT][GPITCH]
-    char* sB = lds + 2 * GSTAGE;     // [2][GT][GPITCH]
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;     // 2 x 4 waves
-    const int tm = blockIdx.x % tiles_m, tn = blockIdx.x / tiles_m;
-    const int64_t row0 = (int64_t)tm * GT, col0 = (int64_t)tn * GT;
-    constexpr int eb = sizeof(typename Operand<OP>::T);
-    const int64_t Kbytes = (int64_t)K * eb;
-    const char* gA = Aq + row0 * Kbytes;
-    const char* gB = Bq + col0 * Kbytes;
-    const int nst = (int)(Kbytes / GBK);
-
-    // each thread moves 4 16-byte chunks of A and 4 of B per stage
-    i4v ra[4], rb[4];
-    auto gload = [&](int st) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int ch = tid + q * 512;          // 0..2047
-            int r = ch >> 3, cb = (ch & 7) * 16;
-            ra[q] = *(const i4v*)(gA + (int64_t)r * Kbytes + (int64_t)st * GBK + cb);
-            rb[q] = *(const i4v*)(gB + (int64_t)r * Kbytes + (int64_t)st * GBK + cb);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int ch = tid + q * 512;
-            int r = ch >> 3, cb = (ch & 7) * 16;
-            *(i4v*)(sA + buf * GSTAGE + r * GPITCH + cb) = ra[q];
-            *(i4v*)(sB + buf * GSTAGE + r * GPITCH + cb) = rb[q];
-        }
-    };
-
-    f16v acc[4][2];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-
-    gload(0);
-    sstore(0);
     __syncthreads();
-    constexpr int KB = Mfma<OP>::KB;
-    const int half = (lane >> 5) * (KB / 2);
-    const int lr = lane & 31;
-    for (int st = 0; st < nst; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nst) gload(st + 1);
-        const char* a_base = sA + buf * GSTAGE + (wm * 128 + lr) * GPITCH + half;
-        const char* b_base = sB + buf * GSTAGE + (wn * 64 + lr) * GPITCH + half;
-#pragma unroll(OP == F8 ? 1 : GBK / KB)
-        for (int ks = 0; ks < GBK / KB; ++ks) {
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = Mfma<OP>::run(a_base + a * 32 * GPITCH + ks * KB, b_base + b * 32 * GPITCH + ks * KB,
-                                              acc[a][b]);
-        }
-        if (st + 1 < nst) sstore(buf ^ 1);
-        __syncthreads();
+    strip_right_solve(S, SP, kbp / 64, Tall + blk * nb * nb, nb, uinv_all + blk * nb * 64, sU);
+    float* out = out_all + blk * nb * nb;
+    for (int e = threadIdx.x; e < SR * kbp; e += 256) {
+        int ii = e % SR, c = e / SR;
+        out[(r0 + ii) + (int64_t)c * nb] = S[ii * SP + c];
     }
-    // epilogue: lane holds, per 32x32 block, column lr and rows 8*(r/4) + 4*(lane/32) + r%4
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t rbase = row0 + wm * 128 + a * 32;
-        const float sa = inv_sa[rbase / 32];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int64_t col = col0 + wn * 64 + b * 32 + lr;
-            if (col >= N) continue;
-            const float d = sa * inv_sb[(col0 + wn * 64 + b * 32) / 32];
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int64_t r = rbase + 8 * g + 4 * (lane >> 5);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    if (r + q < M) {
-                        int64_t idx = (r + q) + col * ldc;
-                        float v = Store<ST>::load(C, idx);
-                        C[idx] = Store<ST>::from_f32(v - acc[a][b][g * 4 + q] * d);
-                    }
-                }
-            }
-        }
+}
+
+__global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const float* __restrict__ Tall,
+                                                   const float* __restrict__ linv_all, float* __restrict__ out_all) {
+    extern __shared__ float smem[];
+    const int64_t blk = blockIdx.y;
+    const int64_t k = blk * nb;
+    const int kb = (int)(n - k < nb ? n - k : nb);
+    const int kbp = (kb + 63) / 64 * 64;
+    const int c0 = SR * blockIdx.x;
+    if (c0 >= kbp) return;
+    const int SP = kbp + 4;
+    float* S = smem;
+    float (*sL)[65] = (float (*)[65])(smem + SR * SP);
+    for (int e = threadIdx.x; e < SR * kbp; e += 256) {
+        int kk = e % kbp, cc = e / kbp;
+        S[cc * SP + kk] = (kk == c0 + cc) ? 1.0f : 0.0f;
+    }
+    __syncthreads();
+    strip_left_solve(S, SP, kbp / 64, Tall + blk * nb * nb, nb, linv_all + blk * nb * 64, sL);
+    float* out = out_all + blk * nb * nb;
+    for (int e = threadIdx.x; e < SR * kbp; e += 256) {
+        int kk = e % kbp, cc = e / kbp;
+        out[kk + (int64_t)(c0 + cc) * nb] = S[cc * SP + kk];
     }
 }
 
@@ -560,8 +476,10 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
                                      (int)trsm_smem(1024)))) return e;
         if ((e = hipFuncSetAttribute((const void*)k_trsm_U<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                      (int)trsm_smem(1024)))) return e;
-        if ((e = hipFuncSetAttribute((const void*)k_gemm_update<OP, ST>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     4 * GSTAGE))) return e;
+        if ((e = hipFuncSetAttribute((const void*)k_inv_upper, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)trsm_smem(1024)))) return e;
+        if ((e = hipFuncSetAttribute((const void*)k_inv_lower, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)trsm_smem(1024)))) return e;
         attr_done = true;
     }
     ST_T* A = (ST_T*)p.A;
@@ -577,6 +495,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
         float* T = p.T + blk * nb * nb;
         float* linv = p.linv + blk * nb * 64;
         float* uinv = p.uinv + blk * nb * 64;
+        prof::begin(s);
         k_diag_load<ST><<<dim3(1, kbp), 256, 0, s>>>(A, lda, k, kb, kbp, T, nb);
         for (int sb = 0; sb < kbp; sb += 64) {
             k_leaf_lu<<<1, 256, 0, s>>>(T, nb, sb, linv + (sb / 64) * 4096, uinv + (sb / 64) * 4096, p.info, k);
@@ -587,19 +506,34 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
             }
         }
         k_diag_store<ST><<<dim3(1, kb), 256, 0, s>>>(A, lda, k, kb, T, nb);
+        prof::end(prof::DIAG, s, 2.0 / 3.0 * kb * (double)kb * kb, 2.0 * kb * (double)kb * sizeof(ST_T));
         if ((e = hipGetLastError())) return e;
         if (m > 0) {
-            const int nstrip = (int)(rup(m, GT) / SR);
+            const int nstrip = (int)(rup(m, 256) / SR);
             const size_t smem = trsm_smem(nb);
+            prof::begin(s);
             k_trsm_L<ST, OP><<<nstrip, 256, smem, s>>>(A, lda, n, k, nb, T, uinv, (OP_T*)p.Lq, p.inv_sa,
                                                        p.lsc + blk * nstrips_total);
             k_trsm_U<ST, OP><<<nstrip, 256, smem, s>>>(A, lda, n, k, nb, T, linv, (OP_T*)p.Uq, p.inv_sb);
-            const int tiles = (int)((m + GT - 1) / GT);
+            prof::end(prof::TRSM, s, 2.0 * m * (double)nb * nb,
+                      4.0 * m * (double)nb * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
+            prof::begin(s);
             ST_T* C = A + (k + kb) + (k + kb) * lda;
-            k_gemm_update<OP, ST><<<tiles * tiles, 512, 4 * GSTAGE, s>>>(C, lda, m, m, nb, (const char*)p.Lq,
-                                                                         (const char*)p.Uq, p.inv_sa, p.inv_sb, tiles);
+            if ((e = gemm_update(OP, ST, C, lda, m, m, nb, p.Lq, p.Uq, p.inv_sa, p.inv_sb, s))) return e;
+            prof::end(prof::GEMM, s, 2.0 * m * (double)m * nb,
+                      2.0 * m * (double)m * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
             if ((e = hipGetLastError())) return e;
         }
+    }
+    // full FP32 inverses of every diagonal block, used by the preconditioner
+    {
+        const int64_t nblk = (n + nb - 1) / nb;
+        dim3 g((unsigned)(nb / SR), (unsigned)nblk);
+        prof::begin(s);
+        k_inv_upper<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.T, p.uinv, p.uinv_full);
+        k_inv_lower<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.T, p.linv, p.linv_full);
+        prof::end(prof::DIAG, s, 2.0 / 3.0 * (double)n * nb * nb, 16.0 * (double)n * nb);
+        if ((e = hipGetLastError())) return e;
     }
     return hipSuccess;
 }

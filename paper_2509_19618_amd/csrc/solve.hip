@@ -11,6 +11,7 @@
 // basis update are deterministic (fixed reduction orders).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "prof.hpp"
 
 namespace mxp {
 
@@ -31,72 +32,72 @@ __global__ __launch_bounds__(256) void k_copy_cols(int64_t n, const double* __re
     for (int r = 0; r < nr; ++r) Z[i + r * ldz] = W[i + r * n];
 }
 
-// Diagonal-block solve, one workgroup per right-hand side (blockIdx.y):
-// lower: z_t = Linv_t (w_t - sum_{u<t} L_tu z_u), t ascending;
-// upper: z_t = Uinv_t (w_t - sum_{u>t} U_tu z_u), t descending.
-// Entries past n (ragged last block) are held at zero.
-template <bool LOWER>
-__global__ __launch_bounds__(256) void k_prec_diag(int64_t n, int64_t k, int kb, int nb, const float* __restrict__ T,
-                                                   const float* __restrict__ inv, double* __restrict__ W) {
-    __shared__ double z[1024];
+// Diagonal-block solve with the full FP32 inverse: Y[k:k+kb] = Inv_k R[k:k+kb]
+// (FP64 arithmetic).  Work-group = 64 rows; its 4 waves split the columns and
+// their partial sums are added in a fixed order.  blockIdx.y = right-hand side.
+__global__ __launch_bounds__(256) void k_prec_diag(int64_t n, int64_t k, int kb, int nb, const float* __restrict__ inv,
+                                                   const double* __restrict__ R, double* __restrict__ Y) {
     __shared__ double part[4][64];
-    double* w = W + (int64_t)blockIdx.y * n + k;
-    const int tid = threadIdx.x;
-    const int kbp = (int)rup(kb, 64);
-    for (int i = tid; i < kbp; i += 256) z[i] = (i < kb) ? w[i] : 0.0;
-    __syncthreads();
-    const int nt = kbp / 64;
-    const int r = tid & 63, q = tid >> 6;  // row r of the 64-block; q splits the inner sums 4 ways
-    for (int step = 0; step < nt; ++step) {
-        const int t = LOWER ? step : nt - 1 - step;
-        // acc = w_t[r] - sum over the other already-solved sub-blocks (split over q)
-        double acc = 0.0;
-        if (LOWER) {
-            for (int u = q; u < t; u += 4)
-                for (int c = 0; c < 64; ++c)
-                    acc += (double)T[(t * 64 + r) + (int64_t)(u * 64 + c) * nb] * z[u * 64 + c];
-        } else {
-            for (int u = t + 1 + q; u < nt; u += 4)
-                for (int c = 0; c < 64; ++c)
-                    acc += (double)T[(t * 64 + r) + (int64_t)(u * 64 + c) * nb] * z[u * 64 + c];
-        }
-        part[q][r] = acc;
-        __syncthreads();
-        double rhs = 0.0;
-        if (q == 0) rhs = z[t * 64 + r] - ((part[0][r] + part[1][r]) + (part[2][r] + part[3][r]));
-        __syncthreads();
-        if (q == 0) z[t * 64 + r] = rhs;
-        __syncthreads();
-        // z_t = inv_t z_t  (64 x 64, split over q by columns)
-        double y = 0.0;
-        for (int c = q * 16; c < q * 16 + 16; ++c) y += (double)inv[(int64_t)t * 4096 + r + 64 * c] * z[t * 64 + c];
-        part[q][r] = y;
-        __syncthreads();
-        if (q == 0) z[t * 64 + r] = (part[0][r] + part[1][r]) + (part[2][r] + part[3][r]);
-        __syncthreads();
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int row = blockIdx.x * 64 + lane;
+    const double* rhs = R + (int64_t)blockIdx.y * n + k;
+    const int q = (kb + 3) / 4;
+    const int c0 = wv * q, c1 = (c0 + q < kb) ? c0 + q : kb;
+    double acc = 0.0;
+    if (row < kb) {
+        const float* col = inv + row;
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) acc += (double)col[(int64_t)c * nb] * rhs[c];
     }
-    for (int i = tid; i < kb; i += 256) w[i] = z[i];
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && row < kb) Y[(int64_t)blockIdx.y * n + k + row] = (part[0][lane] + part[1][lane]) +
+                                                                    (part[2][lane] + part[3][lane]);
 }
 
-// Panel update, thread per row: lower: W[k+kb+i] -= (L21[i,:] / s_i) z ;
-// upper: W[i] -= U[i, k:k+kb] z for i < k.  z = W[k:k+kb] (already solved).
+// Panel update R[rows] -= P z with z = Y[k:k+kb]: lower, rows k+kb..n-1 of
+// L21 (each stored 32-row strip divided by its scale); upper, rows 0..k-1 of
+// the U12 blocks above the diagonal block.  Thread = 2 consecutive rows; the
+// 4 waves split the kb columns; partials added in a fixed order.
 template <int ST, bool LOWER>
 __global__ __launch_bounds__(256) void k_prec_panel(int64_t n, int64_t k, int kb, const typename Store<ST>::T* A,
                                                     int64_t lda, const float* __restrict__ lsc_blk,
-                                                    double* __restrict__ W) {
+                                                    const double* __restrict__ Y, double* __restrict__ R) {
     __shared__ double z[1024];
-    double* w = W + (int64_t)blockIdx.y * n;
-    for (int i = threadIdx.x; i < kb; i += 256) z[i] = w[k + i];
+    __shared__ double part[4][128];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const double* y = Y + (int64_t)blockIdx.y * n + k;
+    double* rhs = R + (int64_t)blockIdx.y * n;
+    for (int i = tid; i < kb; i += 256) z[i] = y[i];
     __syncthreads();
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t row = LOWER ? k + kb + i : i;
-    int64_t rend = LOWER ? n : k;
-    if (row >= rend) return;
-    double acc = 0.0;
-    const typename Store<ST>::T* a = A + row + k * lda;
-    for (int c = 0; c < kb; ++c) acc += (double)Store<ST>::load(a, (int64_t)c * lda) * z[c];
-    if (LOWER) acc /= (double)lsc_blk[row / 32];
-    w[row] -= acc;
+    const int64_t rbeg = LOWER ? k + kb : 0, rend = LOWER ? n : k;
+    const int64_t row = rbeg + (int64_t)blockIdx.x * 128 + 2 * lane;
+    const int q = (kb + 3) / 4;
+    const int c0 = wv * q, c1 = (c0 + q < kb) ? c0 + q : kb;
+    double a0 = 0.0, a1 = 0.0;
+    if (row + 1 < rend) {
+        const typename Store<ST>::T* p = A + row + k * lda;
+#pragma unroll 8
+        for (int c = c0; c < c1; ++c) {
+            const int64_t o = (int64_t)c * lda;
+            a0 += (double)Store<ST>::load(p, o) * z[c];
+            a1 += (double)Store<ST>::load(p, o + 1) * z[c];
+        }
+    } else if (row < rend) {
+        const typename Store<ST>::T* p = A + row + k * lda;
+        for (int c = c0; c < c1; ++c) a0 += (double)Store<ST>::load(p, (int64_t)c * lda) * z[c];
+    }
+    part[wv][2 * lane] = a0;
+    part[wv][2 * lane + 1] = a1;
+    __syncthreads();
+    if (tid < 128) {
+        const int64_t r = rbeg + (int64_t)blockIdx.x * 128 + tid;
+        if (r < rend) {
+            double t = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
+            if (LOWER) t /= (double)lsc_blk[r / 32];
+            rhs[r] -= t;
+        }
+    }
 }
 
 template <int ST>
@@ -106,26 +107,32 @@ static hipError_t prec_typed(const PrecPlan& p, const double* V, int64_t ldv, do
     const int64_t n = p.n, nb = p.nb;
     const int64_t nblk = (n + nb - 1) / nb;
     const int64_t nstrips_total = (n + 31) / 32;
+    double* R = W;                 // right-hand side, updated by the panels
+    double* Y = W + n * nr;        // forward result, then the backward right-hand side
     unsigned rows_g = (unsigned)((n + 255) / 256);
-    k_scale_rows<<<rows_g, 256, 0, s>>>(n, p.rowscale, V, ldv, W, nr);
-    for (int64_t b = 0; b < nblk; ++b) {
+    prof::begin(s);
+    k_scale_rows<<<rows_g, 256, 0, s>>>(n, p.rowscale, V, ldv, R, nr);
+    for (int64_t b = 0; b < nblk; ++b) {         // L y = S v
         int64_t k = b * nb;
         int kb = (int)(n - k < nb ? n - k : nb);
-        k_prec_diag<true><<<dim3(1, nr), 256, 0, s>>>(n, k, kb, (int)nb, p.T + b * nb * nb, p.linv + b * nb * 64, W);
+        k_prec_diag<<<dim3((unsigned)((kb + 63) / 64), nr), 256, 0, s>>>(n, k, kb, (int)nb, p.linv_full + b * nb * nb,
+                                                                        R, Y);
         int64_t m = n - k - kb;
         if (m > 0)
-            k_prec_panel<ST, true><<<dim3((unsigned)((m + 255) / 256), nr), 256, 0, s>>>(
-                n, k, kb, (const T*)p.A, p.lda, p.lsc + b * nstrips_total, W);
+            k_prec_panel<ST, true><<<dim3((unsigned)((m + 127) / 128), nr), 256, 0, s>>>(
+                n, k, kb, (const T*)p.A, p.lda, p.lsc + b * nstrips_total, Y, R);
     }
-    for (int64_t b = nblk - 1; b >= 0; --b) {
+    for (int64_t b = nblk - 1; b >= 0; --b) {    // U z = y
         int64_t k = b * nb;
         int kb = (int)(n - k < nb ? n - k : nb);
-        k_prec_diag<false><<<dim3(1, nr), 256, 0, s>>>(n, k, kb, (int)nb, p.T + b * nb * nb, p.uinv + b * nb * 64, W);
+        k_prec_diag<<<dim3((unsigned)((kb + 63) / 64), nr), 256, 0, s>>>(n, k, kb, (int)nb, p.uinv_full + b * nb * nb,
+                                                                        Y, R);
         if (k > 0)
-            k_prec_panel<ST, false><<<dim3((unsigned)((k + 255) / 256), nr), 256, 0, s>>>(n, k, kb, (const T*)p.A,
-                                                                                        p.lda, nullptr, W);
+            k_prec_panel<ST, false><<<dim3((unsigned)((k + 127) / 128), nr), 256, 0, s>>>(n, k, kb, (const T*)p.A,
+                                                                                        p.lda, nullptr, R, Y);
     }
-    k_copy_cols<<<rows_g, 256, 0, s>>>(n, W, Z, ldz, nr);
+    k_copy_cols<<<rows_g, 256, 0, s>>>(n, R, Z, ldz, nr);
+    prof::end(prof::PREC, s, 2.0 * n * (double)n * nr, (double)n * n * sizeof(T) + 8.0 * n * nb);
     return hipGetLastError();
 }
 

@@ -1,0 +1,63 @@
+"""GPU tests of single kernels through the C ABI.
+
+The trailing update C <- C - diag(ia) Aq Bq^T diag(ib) is checked against its
+definition evaluated in FP64 from the same quantised operands; the bound is
+FP32 accumulation (K+2 roundings of 2^-24 relative to the magnitudes
+involved) plus one rounding to the storage format.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_2509_19618_amd as mxp
+
+pytestmark = pytest.mark.gpu
+
+TORCH_OP = {"f16": torch.float16, "bf16": torch.bfloat16, "f8": torch.float8_e4m3fn, "f32": torch.float32}
+TORCH_ST = {"f16": torch.float16, "bf16": torch.bfloat16, "f32": torch.float32}
+U_ST = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8, "f32": 2.0 ** -24}
+
+
+def _pad(x, m):
+    return (x + m - 1) // m * m
+
+
+@pytest.mark.parametrize("M,N,K,update,store", [
+    (256, 256, 512, "f16", "f16"),
+    (300, 520, 512, "f16", "f16"),
+    (1000, 777, 256, "bf16", "bf16"),
+    (513, 257, 128, "f8", "f16"),
+    (640, 384, 512, "f8", "bf16"),
+    (200, 333, 64, "f32", "f32"),
+    (384, 129, 128, "f16", "f32"),
+    (1, 1, 64, "bf16", "f32"),
+])
+def test_trailing_update_matches_definition(M, N, K, update, store):
+    print("gemm", M, N, K, update, store, flush=True)
+    g = torch.Generator().manual_seed(M * 7 + N)
+    Mp, Np = _pad(M, 256), _pad(N, 256)
+    A = torch.rand((Mp, K), generator=g, dtype=torch.float64) * 2 - 1
+    B = torch.rand((Np, K), generator=g, dtype=torch.float64) * 2 - 1
+    scale_op = 200.0 if update == "f8" else 1.0
+    Aq = (A.float() * scale_op).to(TORCH_OP[update])
+    Bq = (B.float() * scale_op).to(TORCH_OP[update])
+    ia = torch.pow(2.0, torch.randint(-20, -5, (Mp // 32,), generator=g).double()).float()
+    ib = torch.pow(2.0, torch.randint(-8, 3, (Np // 32,), generator=g).double()).float()
+    ldc = M + 3 if store != "f32" else M + 4
+    C = (torch.rand((N, ldc), generator=g, dtype=torch.float64) * 8 - 4).to(TORCH_ST[store])
+    Cd = C.cuda()
+    mxp.mxp_trailing_update(Cd, ldc, M, N, K, update, store, Aq.cuda(), Bq.cuda(), ia.cuda(), ib.cuda())
+    got = Cd.cpu().double()
+    a = Aq.double()[:M].numpy()
+    b = Bq.double()[:N].numpy()
+    da = np.repeat(ia.double().numpy(), 32)[:M]
+    db = np.repeat(ib.double().numpy(), 32)[:N]
+    C0 = C.double().numpy()[:, :M].T           # M x N
+    prod = (a @ b.T) * da[:, None] * db[None, :]
+    ref = C0 - prod
+    mag = np.abs(C0) + (np.abs(a) @ np.abs(b).T) * da[:, None] * db[None, :]
+    bound = U_ST[store] * np.abs(ref) + (K + 2) * 2.0 ** -24 * mag + 1e-30
+    err = np.abs(got.numpy()[:, :M].T - ref)
+    assert np.all(err <= bound), float((err / bound).max())
+    # padding rows of C (ld > M) untouched
+    assert torch.equal(got[:, M:], C.double()[:, M:])
