@@ -73,6 +73,7 @@ static FactorPlan make_plan(int64_t n, int64_t nb, int update, int store, void* 
     AuxLayout al = aux_layout(n, nb);
     char* a = (char*)aux;
     p.T = (float*)(a + al.T);
+    p.Trm = (float*)(a + al.Trm);
     p.linv = (float*)(a + al.linv);
     p.uinv = (float*)(a + al.uinv);
     p.lsc = (float*)(a + al.lsc);

@@ -7,14 +7,9 @@
 //   Aq: M x K operand (K-major rows), Bq: N x K operand (K-major rows),
 //   inv_sa / inv_sb: one power-of-two factor per 32 rows / 32 columns.
 //
-// The accumulator starts at -C * (sa sb) (exact: powers of two), so the
-// read of C is issued before the K loop and hidden behind it; the result is
-// -acc * (inv_sa inv_sb), rounded once to the storage format.
+// The accumulators start at zero and hold sum Aq Bq^T in FP32; the result
+// C - acc * (inv_sa inv_sb) is rounded once to the storage format.
 //
-// Tile 256 x 256, 512 threads = 8 waves in a 2 (M) x 4 (N) grid, each wave
-// 128 x 64 = 4 x 2 blocks of 32 x 32 MFMA output.  K advances 128 bytes per
-// stage through two LDS buffers (row pitch padded to 144 bytes so that the
-// 16-byte fragment reads of 8 consecutive rows hit all 32 banks once).
 // Work-groups are dispatched round-robin over the 8 XCDs; the tile order
 // gives every XCD a contiguous range of tiles, walked in groups of 8 tile
 // rows so that the operand panels in flight on an XCD fit its L2.
@@ -102,28 +97,81 @@ template <> struct Quad<BF16> {
 
 constexpr int GT = 256;           // tile edge
 constexpr int GBK = 128;          // K bytes per stage
-constexpr int GPITCH = GBK + 16;  // LDS row pitch in bytes
-constexpr int GSTAGE = GT * GPITCH;
+constexpr int GSTG = GT * GBK;    // bytes of one operand stage (XOR-swizzled, unpadded)
+constexpr int GCH = GBK / 16;     // 16-byte chunks per operand row
 constexpr int GGROUP = 8;         // tile rows per group in the tile order
 
+// Direct global->LDS copy of 16 bytes per lane: lane L lands at l + 16 L
+// (l is wave-uniform).  gfx950 global_load_lds_dwordx4.
+MXP_DEV void dma16(const char* g, char* l) {
+    __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
+                                     (void __attribute__((address_space(3)))*)l, 16, 0, 0);
+}
+// s_waitcnt vmcnt(0) (expcnt / lgkmcnt not waited)
+MXP_DEV void wait_vm0() { __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8)); }
+
+// byte offset of (row, byte b) in an operand stage: 16-byte chunks XOR-swizzled by row
+MXP_DEV int swz(int row, int b) { return row * GBK + ((((b >> 4) ^ (row & (GCH - 1))) << 4) | (b & 15)); }
+
+template <int OP> struct Frag;
+template <> struct Frag<F16> {
+    typedef h8v T;
+    static MXP_DEV T ld(const char* s, int row, int b) { return *(const h8v*)(s + swz(row, b)); }
+    static MXP_DEV f16v mma(T a, T b, f16v c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
+};
+template <> struct Frag<BF16> {
+    typedef b8v T;
+    static MXP_DEV T ld(const char* s, int row, int b) { return *(const b8v*)(s + swz(row, b)); }
+    static MXP_DEV f16v mma(T a, T b, f16v c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+};
+template <> struct Frag<F32> {
+    typedef float T;
+    static MXP_DEV T ld(const char* s, int row, int b) { return *(const float*)(s + swz(row, b)); }
+    static MXP_DEV f16v mma(T a, T b, f16v c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+};
+template <> struct Frag<F8> {
+    typedef i8v T;
+    static MXP_DEV T ld(const char* s, int row, int b) {
+        i4v a0 = *(const i4v*)(s + swz(row, b)), a1 = *(const i4v*)(s + swz(row, b + 16));
+        i8v x = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+        return x;
+    }
+    // operand formats 0/0 = fp8 e4m3 for both; E8M0 block scales of 1.0
+    static MXP_DEV f16v mma(T a, T b, f16v c) {
+        return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 0x7f7f7f7f, 0, 0x7f7f7f7f);
+    }
+};
+
+// Tile 256 x 256, 256 threads = 4 waves in a 2 x 2 grid, each wave 128 x 128
+// (16 blocks of 32 x 32; accumulators in AGPRs).  Operands: K-major rows,
+// copied 128 bytes of K per stage straight into two XOR-swizzled LDS
+// buffers (no staging registers); the fragments of k-step ks+1 are read
+// from LDS while the 16 MFMAs of k-step ks run.  Epilogue, full tiles with
+// 16-bit C: the freed LDS holds the C tile (read and written with 1 KB
+// coalesced accesses), updated in place in the MFMA layout; other tiles
+// update C directly with guarded accesses.
 template <int OP, int ST>
-__global__ __launch_bounds__(512) void k_gemm_update(typename Store<ST>::T* C, int64_t ldc, int64_t M, int64_t N,
+__global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, int64_t ldc, int64_t M, int64_t N,
                                                      int K, const char* __restrict__ Aq, const char* __restrict__ Bq,
                                                      const float* __restrict__ inv_sa,
                                                      const float* __restrict__ inv_sb, int tiles_m, int tiles_n,
                                                      int per_xcd, int vec_ok) {
     typedef typename Store<ST>::T CT;
+    typedef typename Frag<OP>::T FT;
+    constexpr int KB = Mfma<OP>::KB;
+    constexpr int NKS = GBK / KB;          // k-steps per stage
+    constexpr int RPI = 64 / GCH;          // operand rows per 1 KB copy instruction
+    constexpr int NI = GT / RPI / 4;       // copy instructions per wave, per operand and stage
+    constexpr int CP = GT * (int)sizeof(CT) + 16;  // LDS pitch of a C column in the epilogue
     extern __shared__ __attribute__((aligned(16))) char lds[];
-    char* sA = lds;                  // [2][GT][GPITCH]
-    char* sB = lds + 2 * GSTAGE;     // [2][GT][GPITCH]
+    char* sA = lds;
+    char* sB = lds + 2 * GSTG;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave & 1, wn = wave >> 1;     // 2 x 4 waves
-    // tile order: XCD-contiguous ranges, grouped by GGROUP tile rows
+    const int wm = wave & 1, wn = wave >> 1;
     const int lin = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
     if (lin >= tiles_m * tiles_n) return;
     const int group_size = GGROUP * tiles_n;
-    const int grp = lin / group_size;
-    const int first_m = grp * GGROUP;
+    const int first_m = (lin / group_size) * GGROUP;
     const int gm = (tiles_m - first_m) < GGROUP ? (tiles_m - first_m) : GGROUP;
     const int tm = first_m + (lin % group_size) % gm;
     const int tn = (lin % group_size) / gm;
@@ -134,98 +182,133 @@ __global__ __launch_bounds__(512) void k_gemm_update(typename Store<ST>::T* C, i
     const char* gB = Bq + col0 * Kbytes;
     const int nst = (int)(Kbytes / GBK);
     const int lr = lane & 31, lh = lane >> 5;
-
-    // ---- accumulator <- -C * (sa sb)
-    f16v acc[4][2];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t rb = row0 + wm * 128 + a * 32;
-        const float ia = inv_sa[rb / 32];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int64_t cb = col0 + wn * 64 + b * 32;
-            const float S = -1.0f / (ia * inv_sb[cb / 32]);
-            const int64_t col = cb + lr;
-#pragma unroll
-            for (int g = 0; g < 4; ++g) {
-                const int64_t r = rb + 8 * g + 4 * lh;
-                float v[4] = {0.f, 0.f, 0.f, 0.f};
-                if (col < N) {
-                    const CT* p = C + r + col * ldc;
-                    if (vec_ok && r + 3 < M) Quad<ST>::load(p, v);
-                    else
-                        for (int q = 0; q < 4; ++q)
-                            if (r + q < M) v[q] = Store<ST>::load(p, q);
-                }
-#pragma unroll
-                for (int q = 0; q < 4; ++q) acc[a][b][g * 4 + q] = v[q] * S;
-            }
-        }
-    }
-
-    // each thread moves 4 16-byte chunks of A and 4 of B per stage
-    i4v ra[4], rb[4];
-    auto gload = [&](int st) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int ch = tid + q * 512;          // 0..2047
-            int r = ch >> 3, cb = (ch & 7) * 16;
-            ra[q] = *(const i4v*)(gA + (int64_t)r * Kbytes + (int64_t)st * GBK + cb);
-            rb[q] = *(const i4v*)(gB + (int64_t)r * Kbytes + (int64_t)st * GBK + cb);
-        }
-    };
-    auto sstore = [&](int buf) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            int ch = tid + q * 512;
-            int r = ch >> 3, cb = (ch & 7) * 16;
-            *(i4v*)(sA + buf * GSTAGE + r * GPITCH + cb) = ra[q];
-            *(i4v*)(sB + buf * GSTAGE + r * GPITCH + cb) = rb[q];
-        }
-    };
-
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    constexpr int KB = Mfma<OP>::KB;
-    const int half = lh * (KB / 2);
-    for (int st = 0; st < nst; ++st) {
+    const int l_row = lane / GCH, l_pch = lane % GCH;
+    auto issue = [&](int st) {
         const int buf = st & 1;
-        if (st + 1 < nst) gload(st + 1);
-        const char* a_base = sA + buf * GSTAGE + (wm * 128 + lr) * GPITCH + half;
-        const char* b_base = sB + buf * GSTAGE + (wn * 64 + lr) * GPITCH + half;
-#pragma unroll(OP == F8 ? 1 : GBK / KB)
-        for (int ks = 0; ks < GBK / KB; ++ks) {
+#pragma unroll
+        for (int i = 0; i < NI; ++i) {
+            const int j = wave * NI + i;                      // 1 KB slice of the stage
+            const int row = j * RPI + l_row;
+            const int lch = l_pch ^ (row & (GCH - 1));        // logical chunk stored at this lane's slot
+            const int64_t go = (int64_t)row * Kbytes + (int64_t)st * GBK + lch * 16;
+            dma16(gA + go, sA + buf * GSTG + j * 1024);
+            dma16(gB + go, sB + buf * GSTG + j * 1024);
+        }
+    };
+    f16v acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    issue(0);
+    for (int st = 0; st < nst; ++st) {
+        wait_vm0();
+        __syncthreads();                  // stage st visible; stage st-1's buffer free
+        if (st + 1 < nst) issue(st + 1);
+        const char* A0 = sA + (st & 1) * GSTG;
+        const char* B0 = sB + (st & 1) * GSTG;
+        FT ac[4], bc[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) ac[a] = Frag<OP>::ld(A0, wm * 128 + a * 32 + lr, lh * (KB / 2));
+#pragma unroll
+        for (int b = 0; b < 4; ++b) bc[b] = Frag<OP>::ld(B0, wn * 128 + b * 32 + lr, lh * (KB / 2));
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks) {
+            FT an[4], bn[4];
+            if (ks + 1 < NKS) {
+                const int boff = (ks + 1) * KB + lh * (KB / 2);
+#pragma unroll
+                for (int a = 0; a < 4; ++a) an[a] = Frag<OP>::ld(A0, wm * 128 + a * 32 + lr, boff);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bn[b] = Frag<OP>::ld(B0, wn * 128 + b * 32 + lr, boff);
+            }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b)
-                    acc[a][b] = Mfma<OP>::run(a_base + a * 32 * GPITCH + ks * KB, b_base + b * 32 * GPITCH + ks * KB,
-                                              acc[a][b]);
+                for (int b = 0; b < 4; ++b) acc[a][b] = Frag<OP>::mma(ac[a], bc[b], acc[a][b]);
+            if (ks + 1 < NKS) {
+                // interleave the LDS reads of the next k-step with these MFMAs
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                    __builtin_amdgcn_sched_group_barrier(0x100, OP == F8 ? 2 : 1, 0);
+                }
+#pragma unroll
+                for (int a = 0; a < 4; ++a) ac[a] = an[a];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) bc[b] = bn[b];
+            }
         }
-        if (st + 1 < nst) sstore(buf ^ 1);
-        __syncthreads();
     }
-
-    // ---- C <- -acc * (inv_sa inv_sb); lane holds column lr, rows 8g + 4 lh + q of each block
+    const bool full = vec_ok && (row0 + GT <= M) && (col0 + GT <= N);
+    if constexpr (sizeof(CT) == 2) {
+        if (full) {
+            constexpr int COLB = GT * 2;           // bytes of a tile column
+            constexpr int LPC = COLB / 16;         // lanes per column
+            constexpr int CPI = 64 / LPC;          // columns per wave instruction
+            constexpr int NIT = GT / 4 / CPI;      // instructions per wave
+            const int lc = lane / LPC, lo = (lane % LPC) * 16;
+            __syncthreads();                       // operand buffers no longer read
+#pragma unroll 8
+            for (int it = 0; it < NIT; ++it) {
+                const int c = (wave * NIT + it) * CPI + lc;
+                i4v x = __builtin_nontemporal_load((const i4v*)((const char*)(C + row0 + (col0 + c) * ldc) + lo));
+                *(i4v*)(lds + c * CP + lo) = x;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                const float ia = inv_sa[(row0 + wm * 128 + a * 32) / 32];
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const float d = ia * inv_sb[(col0 + wn * 128 + b * 32) / 32];
+                    const int c = wn * 128 + b * 32 + lr;
+#pragma unroll
+                    for (int g = 0; g < 4; ++g) {
+                        CT* p = (CT*)(lds + c * CP) + wm * 128 + a * 32 + 8 * g + 4 * lh;
+                        float cv[4], v[4];
+                        Quad<ST>::load(p, cv);
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) v[q] = cv[q] - acc[a][b][g * 4 + q] * d;
+                        Quad<ST>::store(p, v);
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll 8
+            for (int it = 0; it < NIT; ++it) {
+                const int c = (wave * NIT + it) * CPI + lc;
+                i4v x = *(const i4v*)(lds + c * CP + lo);
+                __builtin_nontemporal_store(x, (i4v*)((char*)(C + row0 + (col0 + c) * ldc) + lo));
+            }
+            return;
+        }
+    }
+    // direct epilogue (FP32 storage, edge tiles): C - acc * d, quads of 4 rows
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int64_t rb = row0 + wm * 128 + a * 32;
         const float ia = inv_sa[rb / 32];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const int64_t cb = col0 + wn * 64 + b * 32;
-            const float d = -(ia * inv_sb[cb / 32]);
+        for (int b = 0; b < 4; ++b) {
+            const int64_t cb = col0 + wn * 128 + b * 32;
+            const float d = ia * inv_sb[cb / 32];
             const int64_t col = cb + lr;
             if (col >= N) continue;
 #pragma unroll
             for (int g = 0; g < 4; ++g) {
                 const int64_t r = rb + 8 * g + 4 * lh;
-                float v[4];
-#pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = acc[a][b][g * 4 + q] * d;
                 CT* p = C + r + col * ldc;
-                if (vec_ok && r + 3 < M) Quad<ST>::store(p, v);
+                float c[4], v[4];
+                const bool quad = vec_ok && r + 3 < M;
+                if (quad) Quad<ST>::load(p, c);
+                else
+                    for (int q = 0; q < 4; ++q) c[q] = (r + q < M) ? Store<ST>::load(p, q) : 0.0f;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v[q] = c[q] - acc[a][b][g * 4 + q] * d;
+                if (quad) Quad<ST>::store(p, v);
                 else
                     for (int q = 0; q < 4; ++q)
                         if (r + q < M) p[q] = Store<ST>::from_f32(v[q]);
@@ -234,6 +317,8 @@ __global__ __launch_bounds__(512) void k_gemm_update(typename Store<ST>::T* C, i
     }
 }
 
+static constexpr int gemm_lds_bytes() { return 4 * GSTG > GT * (GT * 2 + 16) ? 4 * GSTG : GT * (GT * 2 + 16); }
+
 template <int OP, int ST>
 static hipError_t gemm_typed(void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq, const void* Bq,
                              const float* inv_sa, const float* inv_sb, hipStream_t s) {
@@ -241,15 +326,16 @@ static hipError_t gemm_typed(void* C, int64_t ldc, int64_t M, int64_t N, int K, 
     hipError_t e;
     if (!attr_done) {
         if ((e = hipFuncSetAttribute((const void*)k_gemm_update<OP, ST>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     4 * GSTAGE)))
+                                     gemm_lds_bytes())))
             return e;
         attr_done = true;
     }
     const int tm = (int)((M + GT - 1) / GT), tn = (int)((N + GT - 1) / GT);
     const int nt = tm * tn;
     const int per_xcd = (nt + 7) / 8;
-    const int vec_ok = ((ldc % 4) == 0 && (((uintptr_t)C) % 16) == 0) ? 1 : 0;
-    k_gemm_update<OP, ST><<<8 * per_xcd, 512, 4 * GSTAGE, s>>>((typename Store<ST>::T*)C, ldc, M, N, K,
+    // vectorised C access needs 16-byte aligned columns
+    const int vec_ok = ((ldc * (int64_t)sizeof(typename Store<ST>::T)) % 16 == 0 && (((uintptr_t)C) % 16) == 0) ? 1 : 0;
+    k_gemm_update<OP, ST><<<8 * per_xcd, 256, gemm_lds_bytes(), s>>>((typename Store<ST>::T*)C, ldc, M, N, K,
                                                               (const char*)Aq, (const char*)Bq, inv_sa, inv_sb, tm,
                                                               tn, per_xcd, vec_ok);
     return hipGetLastError();

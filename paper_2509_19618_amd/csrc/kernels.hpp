@@ -24,6 +24,7 @@ struct FactorPlan {
     void* A;         // the matrix, overwritten by L\U
     // aux (persistent)
     float* T;        // nblk x nb x nb: FP32 L11\U11 of every diagonal block
+    float* Trm;      // nblk x nb x nb: the same, row-major
     float* linv;     // nblk x (nb/64) x 64 x 64: inverses of the unit-lower 64x64 diagonal sub-blocks
     float* uinv;     // same for U
     float* lsc;      // nblk x ceil(n/32): power-of-two scale of every stored 32-row strip of L21
@@ -39,7 +40,7 @@ struct FactorPlan {
 };
 
 struct AuxLayout {
-    size_t T, linv, uinv, lsc, rowscale, linv_full, uinv_full, total;
+    size_t T, Trm, linv, uinv, lsc, rowscale, linv_full, uinv_full, total;
 };
 struct WorkLayout {
     size_t Lq, Uq, inv_sa, inv_sb, info, total;

@@ -36,6 +36,7 @@ AuxLayout aux_layout(int64_t n, int64_t nb) {
     int64_t nblk = (n + nb - 1) / nb;
     size_t off = 0;
     L.T = off; off = al256(off + (size_t)nblk * nb * nb * 4);
+    L.Trm = off; off = al256(off + (size_t)nblk * nb * nb * 4);
     L.linv = off; off = al256(off + (size_t)nblk * nb * 64 * 4);
     L.uinv = off; off = al256(off + (size_t)nblk * nb * 64 * 4);
     L.lsc = off; off = al256(off + (size_t)nblk * ((n + 31) / 32) * 4);
@@ -113,17 +114,27 @@ __global__ __launch_bounds__(256) void k_diag_load(const typename Store<ST>::T* 
     }
 }
 
-// A11 (storage format) <- T (FP32 L11\U11)
+// A11 (storage format) <- T (FP32 L11\U11); Trm <- T transposed (row-major
+// copy: rows of U11 contiguous), padded part included.
 template <int ST>
-__global__ __launch_bounds__(256) void k_diag_store(typename Store<ST>::T* A, int64_t lda, int64_t k, int kb,
-                                                    const float* T, int ldt) {
-    int j = blockIdx.y;
-    for (int i = threadIdx.x; i < kb; i += 256)
-        A[(k + i) + (k + j) * lda] = Store<ST>::from_f32(T[i + (int64_t)j * ldt]);
+__global__ __launch_bounds__(256) void k_diag_store(typename Store<ST>::T* A, int64_t lda, int64_t k, int kb, int kbp,
+                                                    const float* T, float* Trm, int ldt) {
+    __shared__ float tile[64][65];
+    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
+    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
+    for (int c = g; c < 64; c += 4) {
+        const float v = T[(i0 + r) + (int64_t)(j0 + c) * ldt];
+        tile[r][c] = v;
+        if (i0 + r < kb && j0 + c < kb) A[(k + i0 + r) + (k + j0 + c) * lda] = Store<ST>::from_f32(v);
+    }
+    __syncthreads();
+    for (int c = g; c < 64; c += 4) Trm[(j0 + r) + (int64_t)(i0 + c) * ldt] = tile[c][r];
 }
 
 // LU of the 64x64 tile T[s:s+64, s:s+64] in LDS, then the inverses of its
-// unit-lower and upper factors by column sweeps.  Thread (r, g): row r,
+// unit-lower and upper factors by column sweeps (L^-1 stored column-major,
+// U^-1 row-major: both are then read along contiguous runs by the MFMA
+// operand loads of the strip solves).  Thread (r, g): row r,
 // columns g, g+4, ...  A zero or non-finite pivot records its 1-based
 // global column in *info (atomic min).
 __global__ __launch_bounds__(256) void k_leaf_lu(float* T, int ldt, int s, float* linv, float* uinv,
@@ -168,7 +179,7 @@ __global__ __launch_bounds__(256) void k_leaf_lu(float* T, int ldt, int s, float
     for (int c = g; c < 64; c += 4) {
         T[(s + r) + (int64_t)(s + c) * ldt] = a[r][c];
         linv[r + 64 * c] = xl[r][c];
-        uinv[r + 64 * c] = xu[r][c];
+        uinv[64 * r + c] = xu[r][c];   // row-major (U^-1 read by rows)
     }
 }
 
@@ -199,11 +210,10 @@ __global__ __launch_bounds__(256) void k_inner_trsm(float* T, int ldt, int s, in
     bool lower = w < R;
     int t = s + 64 + 64 * (lower ? w : w - R);
     int64_t r0 = lower ? t : s, c0 = lower ? s : t;
-    const float* inv = lower ? uinv : linv;
     for (int e = tid; e < 4096; e += 256) {
         int i = e & 63, j = e >> 6;
         sX[i][j] = T[(r0 + i) + (c0 + j) * ldt];
-        sI[i][j] = inv[i + 64 * j];
+        sI[i][j] = lower ? uinv[64 * i + j] : linv[i + 64 * j];
     }
     __syncthreads();
     float c[4][4] = {};
@@ -241,89 +251,113 @@ __global__ __launch_bounds__(256) void k_inner_update(float* T, int ldt, int s, 
 // ============================================================== strip TRSMs + rounding
 constexpr int SR = 32;  // rows (columns) per strip of L21 (U12) and per scale
 
-// Blocked substitution on a 32-row strip held in LDS (row pitch SP):
-// X_J <- (X_J - sum_{I<J} X_I U_IJ) Uinv_J for the nbk 64-column blocks J,
-// with U_IJ read from T (FP32, ld ldt) and Uinv_J the 64x64 inverses.
-__device__ void strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ldt,
-                                  const float* __restrict__ uinv, float (*sU)[65]) {
-    const int tid = threadIdx.x;
-    const int cc = tid & 63, rb = (tid >> 6) * 8;  // this thread: column cc, rows rb..rb+7
+// The strip solves run on the FP32 matrix cores (v_mfma_f32_32x32x2f32):
+// lane l holds A[l%32][k0 + l/32] and B[k0 + l/32][l%32]; the 32x32 result
+// sits in 16 registers, register q of lane l being row 8(q/4) + 4(l/32) + q%4,
+// column l%32.  The strip lives in LDS (pitch odd, so the 32 rows / columns
+// a fragment touches fall in distinct banks); the factor blocks stream from
+// L2 straight into operand registers along contiguous runs.
+typedef float f16v_t __attribute__((ext_vector_type(16)));
+
+MXP_DEV f16v_t mfma2(float a, float b, f16v_t c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+
+// add the other K-half's partial results (waves 2,3 -> waves 0,1) through LDS
+MXP_DEV void khalf_reduce(f16v_t& acc, float* red, int blk, int kh, int lane) {
+    if (kh == 1)
+        for (int q = 0; q < 16; ++q) red[(blk * 16 + q) * 64 + lane] = acc[q];
+    __syncthreads();
+    if (kh == 0)
+        for (int q = 0; q < 16; ++q) acc[q] += red[(blk * 16 + q) * 64 + lane];
+}
+
+// Right solve of a 32-row strip S (row i at S + i*SP): X <- S U^-1 block by
+// block, X_J = (S_J - sum_{I<J} X_I U_IJ) Uinv_J.  Urm: U11 row-major (ld),
+// uinv_rm: the 64x64 diagonal-block inverses, row-major.
+__device__ void strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ Urm, int ld,
+                                  const float* __restrict__ uinv_rm, float* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
     for (int J = 0; J < nbk; ++J) {
-        float acc[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) acc[r] = S[(rb + r) * SP + J * 64 + cc];
+        const int jc = J * 64 + blk * 32 + lr;            // this lane's column of the output block
+        f16v_t acc = {};
         for (int I = 0; I < J; ++I) {
-            for (int e = tid; e < 4096; e += 256) {
-                int i = e & 63, j = e >> 6;
-                sU[i][j] = T[(I * 64 + i) + (int64_t)(J * 64 + j) * ldt];
+            const int kb0 = I * 64 + kh * 32 + lh;
+            float bv[16];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) bv[s2] = Urm[(int64_t)(kb0 + 2 * s2) * ld + jc];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(S[lr * SP + kb0 + 2 * s2], bv[s2], acc);
+        }
+        khalf_reduce(acc, red, blk, kh, lane);
+        if (kh == 0)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = 8 * (q >> 2) + 4 * lh + (q & 3);
+                S[i * SP + jc] -= acc[q];
             }
-            __syncthreads();
-            for (int kk = 0; kk < 64; ++kk) {
-                float u = sU[kk][cc];
+        __syncthreads();
+        f16v_t y = {};
+        {
+            const int k0 = kh * 32 + lh;
+            float bv[16];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) acc[r] = fmaf(-S[(rb + r) * SP + I * 64 + kk], u, acc[r]);
+            for (int s2 = 0; s2 < 16; ++s2) bv[s2] = uinv_rm[(int64_t)J * 4096 + (k0 + 2 * s2) * 64 + blk * 32 + lr];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) y = mfma2(S[lr * SP + J * 64 + k0 + 2 * s2], bv[s2], y);
+        }
+        khalf_reduce(y, red, blk, kh, lane);
+        if (kh == 0)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = 8 * (q >> 2) + 4 * lh + (q & 3);
+                S[i * SP + jc] = y[q];
             }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int r = 0; r < 8; ++r) S[(rb + r) * SP + J * 64 + cc] = acc[r];
-        for (int e = tid; e < 4096; e += 256) {
-            int i = e & 63, j = e >> 6;
-            sU[i][j] = uinv[(int64_t)J * 4096 + i + 64 * j];
-        }
-        __syncthreads();
-        float y[8] = {};
-        for (int kk = 0; kk < 64; ++kk) {
-            float u = sU[kk][cc];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) y[r] = fmaf(S[(rb + r) * SP + J * 64 + kk], u, y[r]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 8; ++r) S[(rb + r) * SP + J * 64 + cc] = y[r];
         __syncthreads();
     }
 }
 
-// Blocked substitution on a 32-column strip held in LDS as S[col * SP + row]:
-// Y_I <- Linv_I (Y_I - sum_{J<I} L_IJ Y_J) for the nbk 64-row blocks I.
-__device__ void strip_left_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ldt,
-                                 const float* __restrict__ linv, float (*sL)[65]) {
-    const int tid = threadIdx.x;
-    const int kr = tid & 63, cb = (tid >> 6) * 8;  // row kr of the 64-block, columns cb..cb+7
+// Left solve of a 32-column strip S (column j at S + j*SP): Y <- L^-1 S,
+// Y_I = Linv_I (S_I - sum_{J<I} L_IJ Y_J).  T: L11 column-major (ld),
+// linv: the 64x64 diagonal-block inverses, column-major.
+__device__ void strip_left_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ld,
+                                 const float* __restrict__ linv, float* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
     for (int I = 0; I < nbk; ++I) {
-        float acc[8];
-#pragma unroll
-        for (int r = 0; r < 8; ++r) acc[r] = S[(cb + r) * SP + I * 64 + kr];
+        const int ir = I * 64 + blk * 32 + lr;            // this lane's row of L for the A operand
+        f16v_t acc = {};
         for (int J = 0; J < I; ++J) {
-            for (int e = tid; e < 4096; e += 256) {
-                int i = e >> 6, j = e & 63;
-                sL[i][j] = T[(I * 64 + i) + (int64_t)(J * 64 + j) * ldt];
+            const int kb0 = J * 64 + kh * 32 + lh;
+            float av[16];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) av[s2] = T[ir + (int64_t)(kb0 + 2 * s2) * ld];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(av[s2], S[lr * SP + kb0 + 2 * s2], acc);
+        }
+        khalf_reduce(acc, red, blk, kh, lane);
+        if (kh == 0)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = I * 64 + blk * 32 + 8 * (q >> 2) + 4 * lh + (q & 3);
+                S[lr * SP + i] -= acc[q];
             }
-            __syncthreads();
-            for (int t = 0; t < 64; ++t) {
-                float l = sL[kr][t];
+        __syncthreads();
+        f16v_t y = {};
+        {
+            const int k0 = kh * 32 + lh;
+            float av[16];
 #pragma unroll
-                for (int r = 0; r < 8; ++r) acc[r] = fmaf(-l, S[(cb + r) * SP + J * 64 + t], acc[r]);
+            for (int s2 = 0; s2 < 16; ++s2) av[s2] = linv[(int64_t)I * 4096 + (blk * 32 + lr) + 64 * (k0 + 2 * s2)];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) y = mfma2(av[s2], S[lr * SP + I * 64 + k0 + 2 * s2], y);
+        }
+        khalf_reduce(y, red, blk, kh, lane);
+        if (kh == 0)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int i = I * 64 + blk * 32 + 8 * (q >> 2) + 4 * lh + (q & 3);
+                S[lr * SP + i] = y[q];
             }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int r = 0; r < 8; ++r) S[(cb + r) * SP + I * 64 + kr] = acc[r];
-        for (int e = tid; e < 4096; e += 256) {
-            int i = e >> 6, j = e & 63;
-            sL[i][j] = linv[(int64_t)I * 4096 + i + 64 * j];
-        }
-        __syncthreads();
-        float y[8] = {};
-        for (int t = 0; t < 64; ++t) {
-            float l = sL[kr][t];
-#pragma unroll
-            for (int r = 0; r < 8; ++r) y[r] = fmaf(l, S[(cb + r) * SP + I * 64 + t], y[r]);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 8; ++r) S[(cb + r) * SP + I * 64 + kr] = y[r];
         __syncthreads();
     }
 }
@@ -341,17 +375,20 @@ __device__ float strip_amax(const float* S, int SP, int width) {
     return amax;
 }
 
+// LDS of a strip kernel: the strip (32 x (nb+1) floats) and the K-half reduction buffer
+static inline size_t trsm_smem(int nb) { return (size_t)(SR * (nb + 1) + 2 * 16 * 64) * sizeof(float); }
+
 // L21 strip: X (32 x nb) = A21[rows, :] U11^-1, then amax -> power-of-two
 // scales; writes the operand Lq (K-major, update format, scaled), the stored
 // L21 (storage format, scaled) and the scales.
 template <int ST, int OP>
 __global__ __launch_bounds__(256) void k_trsm_L(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
-                                                const float* __restrict__ T, const float* __restrict__ uinv,
+                                                const float* __restrict__ Urm, const float* __restrict__ uinv,
                                                 typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk) {
     extern __shared__ float smem[];
-    const int SP = nb + 4;
+    const int SP = nb + 1;
     float* S = smem;
-    float (*sU)[65] = (float (*)[65])(smem + SR * SP);
+    float* red = smem + SR * SP;
     const int tid = threadIdx.x, w = blockIdx.x;
     const int64_t r0 = k + nb + (int64_t)SR * w;
     int64_t rv = n - r0;
@@ -361,7 +398,7 @@ __global__ __launch_bounds__(256) void k_trsm_L(typename Store<ST>::T* A, int64_
         S[ii * SP + c] = (ii < rv) ? Store<ST>::load(A, (r0 + ii) + (k + c) * lda) : 0.0f;
     }
     __syncthreads();
-    strip_right_solve(S, SP, nb / 64, T, nb, uinv, sU);
+    strip_right_solve(S, SP, nb / 64, Urm, nb, uinv, red);
     const float amax = strip_amax(S, SP, nb);
     const float s_op = Operand<OP>::scaled ? pow2_scale(amax, Operand<OP>::scale_exp) : 1.0f;
     const float s_st = Store<ST>::scaled ? pow2_scale(amax, Store<ST>::scale_exp) : 1.0f;
@@ -386,9 +423,9 @@ __global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_
                                                 const float* __restrict__ T, const float* __restrict__ linv,
                                                 typename Operand<OP>::T* Uq, float* inv_sb) {
     extern __shared__ float smem[];
-    const int SP = nb + 4;
+    const int SP = nb + 1;
     float* S = smem;
-    float (*sL)[65] = (float (*)[65])(smem + SR * SP);
+    float* red = smem + SR * SP;
     const int tid = threadIdx.x, w = blockIdx.x;
     const int64_t c0 = k + nb + (int64_t)SR * w;
     int64_t cv = n - c0;
@@ -398,7 +435,7 @@ __global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_
         S[cc * SP + kk] = (cc < cv) ? Store<ST>::load(A, (k + kk) + (c0 + cc) * lda) : 0.0f;
     }
     __syncthreads();
-    strip_left_solve(S, SP, nb / 64, T, nb, linv, sL);
+    strip_left_solve(S, SP, nb / 64, T, nb, linv, red);
     const float amax = strip_amax(S, SP, nb);
     const float s_op = Operand<OP>::scaled ? pow2_scale(amax, Operand<OP>::scale_exp) : 1.0f;
     if (tid == 0) inv_sb[w] = 1.0f / s_op;
@@ -412,7 +449,7 @@ __global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_
 // Full inverses of the diagonal blocks (for the preconditioner), all blocks
 // in one launch: blockIdx.y = block, blockIdx.x = 32-wide strip.
 // U11^-1 rows r0..r0+31 = I[r0:r0+32, :] U11^-1; L11^-1 columns = L11^-1 I[:, c0:c0+32].
-__global__ __launch_bounds__(256) void k_inv_upper(int64_t n, int nb, const float* __restrict__ Tall,
+__global__ __launch_bounds__(256) void k_inv_upper(int64_t n, int nb, const float* __restrict__ Trm_all,
                                                    const float* __restrict__ uinv_all, float* __restrict__ out_all) {
     extern __shared__ float smem[];
     const int64_t blk = blockIdx.y;
@@ -421,15 +458,15 @@ __global__ __launch_bounds__(256) void k_inv_upper(int64_t n, int nb, const floa
     const int kbp = (kb + 63) / 64 * 64;
     const int r0 = SR * blockIdx.x;
     if (r0 >= kbp) return;
-    const int SP = kbp + 4;
+    const int SP = kbp + 1;
     float* S = smem;
-    float (*sU)[65] = (float (*)[65])(smem + SR * SP);
+    float* red = smem + SR * SP;
     for (int e = threadIdx.x; e < SR * kbp; e += 256) {
         int ii = e % SR, c = e / SR;
         S[ii * SP + c] = (r0 + ii == c) ? 1.0f : 0.0f;
     }
     __syncthreads();
-    strip_right_solve(S, SP, kbp / 64, Tall + blk * nb * nb, nb, uinv_all + blk * nb * 64, sU);
+    strip_right_solve(S, SP, kbp / 64, Trm_all + blk * nb * nb, nb, uinv_all + blk * nb * 64, red);
     float* out = out_all + blk * nb * nb;
     for (int e = threadIdx.x; e < SR * kbp; e += 256) {
         int ii = e % SR, c = e / SR;
@@ -446,15 +483,15 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
     const int kbp = (kb + 63) / 64 * 64;
     const int c0 = SR * blockIdx.x;
     if (c0 >= kbp) return;
-    const int SP = kbp + 4;
+    const int SP = kbp + 1;
     float* S = smem;
-    float (*sL)[65] = (float (*)[65])(smem + SR * SP);
+    float* red = smem + SR * SP;
     for (int e = threadIdx.x; e < SR * kbp; e += 256) {
         int kk = e % kbp, cc = e / kbp;
         S[cc * SP + kk] = (kk == c0 + cc) ? 1.0f : 0.0f;
     }
     __syncthreads();
-    strip_left_solve(S, SP, kbp / 64, Tall + blk * nb * nb, nb, linv_all + blk * nb * 64, sL);
+    strip_left_solve(S, SP, kbp / 64, Tall + blk * nb * nb, nb, linv_all + blk * nb * 64, red);
     float* out = out_all + blk * nb * nb;
     for (int e = threadIdx.x; e < SR * kbp; e += 256) {
         int kk = e % kbp, cc = e / kbp;
@@ -463,7 +500,6 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
 }
 
 // ============================================================== driver
-static size_t trsm_smem(int nb) { return (size_t)(SR * (nb + 4) + 64 * 65) * sizeof(float); }
 
 template <int ST, int OP>
 static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
@@ -505,14 +541,14 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
                 k_inner_update<<<R * R, 256, 0, s>>>(T, nb, sb, kbp);
             }
         }
-        k_diag_store<ST><<<dim3(1, kb), 256, 0, s>>>(A, lda, k, kb, T, nb);
+        k_diag_store<ST><<<dim3(kbp / 64, kbp / 64), 256, 0, s>>>(A, lda, k, kb, kbp, T, p.Trm + blk * nb * nb, nb);
         prof::end(prof::DIAG, s, 2.0 / 3.0 * kb * (double)kb * kb, 2.0 * kb * (double)kb * sizeof(ST_T));
         if ((e = hipGetLastError())) return e;
         if (m > 0) {
             const int nstrip = (int)(rup(m, 256) / SR);
             const size_t smem = trsm_smem(nb);
             prof::begin(s);
-            k_trsm_L<ST, OP><<<nstrip, 256, smem, s>>>(A, lda, n, k, nb, T, uinv, (OP_T*)p.Lq, p.inv_sa,
+            k_trsm_L<ST, OP><<<nstrip, 256, smem, s>>>(A, lda, n, k, nb, p.Trm + blk * nb * nb, uinv, (OP_T*)p.Lq, p.inv_sa,
                                                        p.lsc + blk * nstrips_total);
             k_trsm_U<ST, OP><<<nstrip, 256, smem, s>>>(A, lda, n, k, nb, T, linv, (OP_T*)p.Uq, p.inv_sb);
             prof::end(prof::TRSM, s, 2.0 * m * (double)nb * nb,
@@ -530,7 +566,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
         const int64_t nblk = (n + nb - 1) / nb;
         dim3 g((unsigned)(nb / SR), (unsigned)nblk);
         prof::begin(s);
-        k_inv_upper<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.T, p.uinv, p.uinv_full);
+        k_inv_upper<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.Trm, p.uinv, p.uinv_full);
         k_inv_lower<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.T, p.linv, p.linv_full);
         prof::end(prof::DIAG, s, 2.0 / 3.0 * (double)n * nb * nb, 16.0 * (double)n * nb);
         if ((e = hipGetLastError())) return e;
