@@ -70,6 +70,7 @@ static FactorPlan make_plan(int64_t n, int64_t nb, int update, int store, void* 
                             void* work) {
     FactorPlan p;
     p.n = n; p.nb = nb; p.lda = lda; p.update = update; p.store = store; p.A = A;
+    p.op_rows = operand_rows(n);
     AuxLayout al = aux_layout(n, nb);
     char* a = (char*)aux;
     p.T = (float*)(a + al.T);
@@ -316,9 +317,9 @@ extern "C" int mxp_trailing_update(int64_t M, int64_t N, int64_t K, int update, 
     if (M < 0 || N < 0 || K < 1 || K > 4096 || ldc < (M > 1 ? M : 1) || !valid_pair(update, store) ||
         (K * dtype_bytes(update)) % 128 || (M > 0 && N > 0 && (!C || !Aq || !Bq || !inv_sa || !inv_sb)))
         return set_err(MXP_EINVAL, "mxp_trailing_update: bad argument%s", "");
-    prof::begin((hipStream_t)stream);
+    hipEvent_t pt = prof::begin((hipStream_t)stream);
     HIPCHK(gemm_update(update, store, C, ldc, M, N, (int)K, Aq, Bq, inv_sa, inv_sb, (hipStream_t)stream));
-    prof::end(prof::GEMM, (hipStream_t)stream, 2.0 * M * (double)N * K,
+    prof::end(pt, prof::GEMM, (hipStream_t)stream, 2.0 * M * (double)N * K,
               2.0 * M * (double)N * dtype_bytes(store) + (double)(M + N) * K * dtype_bytes(update));
     return MXP_OK;
 }

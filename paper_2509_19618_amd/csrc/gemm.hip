@@ -155,7 +155,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, i
                                                      int K, const char* __restrict__ Aq, const char* __restrict__ Bq,
                                                      const float* __restrict__ inv_sa,
                                                      const float* __restrict__ inv_sb, int tiles_m, int tiles_n,
-                                                     int per_xcd, int vec_ok) {
+                                                     int per_xcd, int slots, int vec_ok) {
     typedef typename Store<ST>::T CT;
     typedef typename Frag<OP>::T FT;
     constexpr int KB = Mfma<OP>::KB;
@@ -168,8 +168,12 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, i
     char* sB = lds + 2 * GSTG;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    const int lin = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
-    if (lin >= tiles_m * tiles_n) return;
+    // persistent: work-group j of XCD x (x = blockIdx % 8) walks tiles
+    // x*per_xcd + j, + slots, + 2 slots, ... of its XCD's contiguous range
+    const int xcd = (int)(blockIdx.x % 8);
+    const int xend = min((xcd + 1) * per_xcd, tiles_m * tiles_n);
+    for (int lin = xcd * per_xcd + (int)(blockIdx.x / 8); lin < xend; lin += slots) {
+    __syncthreads();                      // LDS of the previous tile no longer read
     const int group_size = GGROUP * tiles_n;
     const int first_m = (lin / group_size) * GGROUP;
     const int gm = (tiles_m - first_m) < GGROUP ? (tiles_m - first_m) : GGROUP;
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, i
                 i4v x = *(const i4v*)(lds + c * CP + lo);
                 __builtin_nontemporal_store(x, (i4v*)((char*)(C + row0 + (col0 + c) * ldc) + lo));
             }
-            return;
+            continue;
         }
     }
     // direct epilogue (FP32 storage, edge tiles): C - acc * d, quads of 4 rows
@@ -315,6 +319,7 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, i
             }
         }
     }
+    }  // tile loop
 }
 
 static constexpr int gemm_lds_bytes() { return 4 * GSTG > GT * (GT * 2 + 16) ? 4 * GSTG : GT * (GT * 2 + 16); }
@@ -333,11 +338,14 @@ static hipError_t gemm_typed(void* C, int64_t ldc, int64_t M, int64_t N, int K, 
     const int tm = (int)((M + GT - 1) / GT), tn = (int)((N + GT - 1) / GT);
     const int nt = tm * tn;
     const int per_xcd = (nt + 7) / 8;
+    // one work-group per tile: the dispatcher then interleaves work-groups of
+    // kernels on other streams as tiles retire
+    const int slots = per_xcd;
     // vectorised C access needs 16-byte aligned columns
     const int vec_ok = ((ldc * (int64_t)sizeof(typename Store<ST>::T)) % 16 == 0 && (((uintptr_t)C) % 16) == 0) ? 1 : 0;
-    k_gemm_update<OP, ST><<<8 * per_xcd, 256, gemm_lds_bytes(), s>>>((typename Store<ST>::T*)C, ldc, M, N, K,
+    k_gemm_update<OP, ST><<<8 * slots, 256, gemm_lds_bytes(), s>>>((typename Store<ST>::T*)C, ldc, M, N, K,
                                                               (const char*)Aq, (const char*)Bq, inv_sa, inv_sb, tm,
-                                                              tn, per_xcd, vec_ok);
+                                                              tn, per_xcd, slots, vec_ok);
     return hipGetLastError();
 }
 

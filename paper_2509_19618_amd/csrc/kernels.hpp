@@ -32,10 +32,11 @@ struct FactorPlan {
     float* linv_full;  // nblk x nb x nb: L11^-1 of every diagonal block (FP32, ld nb)
     float* uinv_full;  // nblk x nb x nb: U11^-1
     // work (scratch)
-    void* Lq;        // Mpad x nb operand (K-major)
-    void* Uq;        // Npad x nb operand (K-major)
-    float* inv_sa;   // Mpad/32
-    float* inv_sb;   // Npad/32
+    int64_t op_rows; // rows of one operand set (operand_rows(n))
+    void* Lq;        // 2 sets of op_rows x nb operands (K-major)
+    void* Uq;        // 2 sets of op_rows x nb operands (K-major)
+    float* inv_sa;   // 2 sets of op_rows/32
+    float* inv_sb;   // 2 sets of op_rows/32
     unsigned long long* info;  // 1
 };
 
@@ -46,9 +47,11 @@ struct WorkLayout {
     size_t Lq, Uq, inv_sa, inv_sb, info, total;
 };
 AuxLayout aux_layout(int64_t n, int64_t nb);
+int64_t operand_rows(int64_t n);
 WorkLayout work_layout(int64_t n, int64_t nb, int update);
 int dtype_bytes(int dt);
 
+// CUs the trailing update leaves free (set around the look-ahead steps)
 // C (M x N, storage) <- C - diag(inv_sa) Aq Bq^T diag(inv_sb); Aq/Bq rows padded to 256
 hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq,
                        const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s);

@@ -47,15 +47,19 @@ AuxLayout aux_layout(int64_t n, int64_t nb) {
     return L;
 }
 
+// operand rows per set: the trailing size padded to 256, plus 256 so that
+// the sub-range updates of the look-ahead (starting nb rows in) stay inside
+int64_t operand_rows(int64_t n) { return rup(n, 256) + 256; }
+
 WorkLayout work_layout(int64_t n, int64_t nb, int update) {
     WorkLayout W;
-    int64_t mpad = rup(n, 256);
+    int64_t rows = operand_rows(n);
     size_t eb = (size_t)dtype_bytes(update);
     size_t off = 0;
-    W.Lq = off; off = al256(off + (size_t)mpad * nb * eb);
-    W.Uq = off; off = al256(off + (size_t)mpad * nb * eb);
-    W.inv_sa = off; off = al256(off + (size_t)(mpad / 32) * 4);
-    W.inv_sb = off; off = al256(off + (size_t)(mpad / 32) * 4);
+    W.Lq = off; off = al256(off + 2 * (size_t)rows * nb * eb);     // two alternating sets
+    W.Uq = off; off = al256(off + 2 * (size_t)rows * nb * eb);
+    W.inv_sa = off; off = al256(off + 2 * (size_t)(rows / 32) * 4);
+    W.inv_sb = off; off = al256(off + 2 * (size_t)(rows / 32) * 4);
     W.info = off; off = al256(off + 8);
     W.total = off;
     return W;
@@ -131,121 +135,168 @@ __global__ __launch_bounds__(256) void k_diag_store(typename Store<ST>::T* A, in
     for (int c = g; c < 64; c += 4) Trm[(j0 + r) + (int64_t)(i0 + c) * ldt] = tile[c][r];
 }
 
-// LU of the 64x64 tile T[s:s+64, s:s+64] in LDS, then the inverses of its
-// unit-lower and upper factors by column sweeps (L^-1 stored column-major,
-// U^-1 row-major: both are then read along contiguous runs by the MFMA
-// operand loads of the strip solves).  Thread (r, g): row r,
-// columns g, g+4, ...  A zero or non-finite pivot records its 1-based
-// global column in *info (atomic min).
-__global__ __launch_bounds__(256) void k_leaf_lu(float* T, int ldt, int s, float* linv, float* uinv,
-                                                 unsigned long long* info, int64_t col0) {
+// LU of the 64x64 tile T[s:s+64, s:s+64], then the inverses of its
+// unit-lower and upper factors.  1024 threads: thread (r, g) keeps row r,
+// columns g, g+16, g+32, g+48 in registers; each elimination step
+// broadcasts the pivot row and column through LDS (two buffers alternate,
+// so one barrier per step suffices).  Sixteen waves keep the four SIMDs
+// busy across the short dependent chain of every step.  L^-1 is stored
+// column-major and U^-1 row-major: both are then read along contiguous runs
+// by the MFMA operand loads of the strip solves.  A zero or non-finite pivot
+// records its 1-based global column in *info (atomic min).
+constexpr int LEAF_THREADS = 1024;
+__global__ __launch_bounds__(LEAF_THREADS) void k_leaf_lu(float* T, int ldt, int s, float* linv, float* uinv,
+                                                          unsigned long long* info, int64_t col0) {
     __shared__ float a[64][65];
-    __shared__ float xl[64][65];
-    __shared__ float xu[64][65];
-    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
-    for (int c = g; c < 64; c += 4) {
-        a[r][c] = T[(s + r) + (int64_t)(s + c) * ldt];
-        xl[r][c] = (r == c) ? 1.0f : 0.0f;
-        xu[r][c] = (r == c) ? 1.0f : 0.0f;
-    }
-    __syncthreads();
+    __shared__ float rowb[2][64], colb[2][64];
+    __shared__ float rl[2][64], ru[2][64];
+    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;   // g in 0..15
+    float v[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = T[(s + r) + (int64_t)(s + g + 16 * t) * ldt];
+#pragma unroll 1
     for (int j = 0; j < 64; ++j) {
-        const float p = a[j][j];
-        if (tid == 0 && (p == 0.0f || !isfinite(p))) atomicMin(info, (unsigned long long)(col0 + s + j + 1));
-        if (g == 0 && r > j) a[r][j] = a[r][j] / p;
-        __syncthreads();
-        if (r > j) {
-            const float l = a[r][j];
-            for (int c = j + 1 + g; c < 64; c += 4) a[r][c] -= l * a[j][c];
+        const int b = j & 1, jt = j >> 4;
+        const float vj = (jt == 0) ? v[0] : (jt == 1) ? v[1] : (jt == 2) ? v[2] : v[3];
+        if (g == (j & 15)) colb[b][r] = vj;
+        if (r == j) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) rowb[b][g + 16 * t] = v[t];
         }
         __syncthreads();
+        const float rp = 1.0f / rowb[b][j];
+        if (r > j) {
+            const float l = colb[b][r] * rp;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int c = g + 16 * t;
+                const float upd = v[t] - l * rowb[b][c];
+                v[t] = (c > j) ? upd : ((c == j) ? l : v[t]);
+            }
+        }
     }
-    // L^-1: X = I; for t ascending, rows i > t: X[i][0:t] -= L[i][t] X[t][0:t]
-    // U^-1: X = I; for t descending: X[t][:] /= U[t][t]; rows i < t: X[i][t:] -= U[i][t] X[t][t:]
-    for (int t = 0; t < 64; ++t) {
-        const int tu = 63 - t;
-        if (g == 0) xu[tu][r] = xu[tu][r] / a[tu][tu];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int c = g + 16 * t;
+        T[(s + r) + (int64_t)(s + c) * ldt] = v[t];
+        a[r][c] = v[t];
+        // the pivots are the final diagonal of U: report the first zero / non-finite one
+        if (c == r && (v[t] == 0.0f || !isfinite(v[t]))) atomicMin(info, (unsigned long long)(col0 + s + r + 1));
+    }
+    __syncthreads();
+    // L^-1: X = I; for t ascending, rows i > t: X[i][:] -= L[i][t] X[t][:]
+    // U^-1: X = I; for t descending: X[t][:] /= U[t][t]; rows i < t: X[i][:] -= U[i][t] X[t][:]
+    float xl[4], xu[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        xl[t] = (r == g + 16 * t) ? 1.0f : 0.0f;
+        xu[t] = xl[t];
+    }
+#pragma unroll 1
+    for (int q = 0; q < 64; ++q) {
+        const int t = q, tu = 63 - q, b = q & 1;
+        if (r == t) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) rl[b][g + 16 * u] = xl[u];
+        }
+        if (r == tu) {
+            const float d = a[tu][tu];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                xu[u] = xu[u] / d;
+                ru[b][g + 16 * u] = xu[u];
+            }
+        }
         __syncthreads();
         if (r > t) {
             const float l = a[r][t];
-            for (int c = g; c <= t; c += 4) xl[r][c] -= l * xl[t][c];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xl[u] -= l * rl[b][g + 16 * u];
         }
         if (r < tu) {
-            const float u = a[r][tu];
-            for (int c = tu + g; c < 64; c += 4) xu[r][c] -= u * xu[tu][c];
+            const float w = a[r][tu];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) xu[u] -= w * ru[b][g + 16 * u];
         }
-        __syncthreads();
     }
-    for (int c = g; c < 64; c += 4) {
-        T[(s + r) + (int64_t)(s + c) * ldt] = a[r][c];
-        linv[r + 64 * c] = xl[r][c];
-        uinv[64 * r + c] = xu[r][c];   // row-major (U^-1 read by rows)
-    }
-}
-
-// 64x64x64 FP32 product on LDS tiles: each of 256 threads owns a 4x4 block
-// (rows 4*(tid/16).., cols 4*(tid%16)..) of C += A B.
-__device__ __forceinline__ void tile64_fma(const float (*sA)[65], const float (*sB)[65], float c[4][4], int tid) {
-    int r0 = (tid >> 4) * 4, c0 = (tid & 15) * 4;
-#pragma unroll 8
-    for (int k = 0; k < 64; ++k) {
-        float av[4], bv[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) { av[q] = sA[r0 + q][k]; bv[q] = sB[k][c0 + q]; }
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-#pragma unroll
-            for (int u = 0; u < 4; ++u) c[q][u] = fmaf(av[q], bv[u], c[q][u]);
+    for (int u = 0; u < 4; ++u) {
+        const int c = g + 16 * u;
+        linv[r + 64 * c] = xl[u];   // column-major
+        uinv[64 * r + c] = xu[u];   // row-major
     }
 }
 
-// Inner step s: tiles T[I, s] <- T[I, s] Uinv_s (I > s) and T[s, J] <- Linv_s T[s, J] (J > s)
+typedef float f16v_t __attribute__((ext_vector_type(16)));
+MXP_DEV f16v_t mfma2(float a, float b, f16v_t c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
+
+// Inner step s of the diagonal-block LU, on the FP32 matrix cores.  Four
+// waves, each a 32x32 block of a 64x64 tile (MFMA 32x32x2: lane l holds
+// A[l%32][k0 + l/32], B[k0 + l/32][l%32]; register q of the result is row
+// 8(q/4) + 4(l/32) + q%4, column l%32).
+//   trsm:   T[I, s] <- T[I, s] Uinv_s (I > s) and T[s, J] <- Linv_s T[s, J] (J > s)
+//   update: T[I, J] -= T[I, s] T[s, J]  (I, J > s)
 __global__ __launch_bounds__(256) void k_inner_trsm(float* T, int ldt, int s, int kbp, const float* linv,
                                                     const float* uinv) {
-    __shared__ float sX[64][65];
-    __shared__ float sI[64][65];
-    int tid = threadIdx.x;
-    int R = (kbp - s - 64) / 64;
-    int w = blockIdx.x;
-    bool lower = w < R;
-    int t = s + 64 + 64 * (lower ? w : w - R);
-    int64_t r0 = lower ? t : s, c0 = lower ? s : t;
-    for (int e = tid; e < 4096; e += 256) {
-        int i = e & 63, j = e >> 6;
-        sX[i][j] = T[(r0 + i) + (c0 + j) * ldt];
-        sI[i][j] = lower ? uinv[64 * i + j] : linv[i + 64 * j];
+    __shared__ float sB[64][65];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 31, lh = lane >> 5, wr = wave & 1, wc = wave >> 1;
+    const int R = (kbp - s - 64) / 64;
+    const int w = blockIdx.x;
+    const bool lower = w < R;
+    const int t = s + 64 + 64 * (lower ? w : w - R);
+    const int64_t r0 = lower ? t : s, c0 = lower ? s : t;
+    f16v_t acc = {};
+    if (lower) {
+        // X (rows t.., cols s..) times Uinv (row-major): A from T, B from uinv, both read along contiguous runs
+#pragma unroll 8
+        for (int k2 = 0; k2 < 32; ++k2) {
+            const int k = 2 * k2 + lh;
+            acc = mfma2(T[(r0 + 32 * wr + lr) + (c0 + k) * ldt], uinv[k * 64 + 32 * wc + lr], acc);
+        }
+    } else {
+        // Linv (column-major) times X (rows s.., cols t..): X staged through LDS
+        for (int e = tid; e < 4096; e += 256) {
+            int i = e & 63, j = e >> 6;
+            sB[i][j] = T[(r0 + i) + (c0 + j) * ldt];
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int k2 = 0; k2 < 32; ++k2) {
+            const int k = 2 * k2 + lh;
+            acc = mfma2(linv[(32 * wr + lr) + 64 * k], sB[k][32 * wc + lr], acc);
+        }
     }
-    __syncthreads();
-    float c[4][4] = {};
-    if (lower) tile64_fma(sX, sI, c, tid);  // X Uinv
-    else tile64_fma(sI, sX, c, tid);        // Linv X
-    int rr = (tid >> 4) * 4, cc = (tid & 15) * 4;
+    __syncthreads();   // every wave has read the block before it is overwritten
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) T[(r0 + rr + q) + (c0 + cc + u) * ldt] = c[q][u];
+    for (int q = 0; q < 16; ++q) {
+        const int i = 32 * wr + 8 * (q >> 2) + 4 * lh + (q & 3);
+        T[(r0 + i) + (c0 + 32 * wc + lr) * ldt] = acc[q];
+    }
 }
 
-// Inner step s: T[I, J] -= T[I, s] T[s, J] for I, J > s
 __global__ __launch_bounds__(256) void k_inner_update(float* T, int ldt, int s, int kbp) {
-    __shared__ float sA[64][65];
     __shared__ float sB[64][65];
-    int tid = threadIdx.x;
-    int R = (kbp - s - 64) / 64;
-    int I = s + 64 + 64 * (blockIdx.x % R), J = s + 64 + 64 * (blockIdx.x / R);
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 31, lh = lane >> 5, wr = wave & 1, wc = wave >> 1;
+    const int R = (kbp - s - 64) / 64;
+    const int I = s + 64 + 64 * (blockIdx.x % R), J = s + 64 + 64 * (blockIdx.x / R);
     for (int e = tid; e < 4096; e += 256) {
         int i = e & 63, j = e >> 6;
-        sA[i][j] = T[(I + i) + (int64_t)(s + j) * ldt];
         sB[i][j] = T[(s + i) + (int64_t)(J + j) * ldt];
     }
     __syncthreads();
-    float c[4][4] = {};
-    tile64_fma(sA, sB, c, tid);
-    int rr = (tid >> 4) * 4, cc = (tid & 15) * 4;
+    f16v_t acc = {};
+#pragma unroll 8
+    for (int k2 = 0; k2 < 32; ++k2) {
+        const int k = 2 * k2 + lh;
+        acc = mfma2(T[(I + 32 * wr + lr) + (int64_t)(s + k) * ldt], sB[k][32 * wc + lr], acc);
+    }
 #pragma unroll
-    for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int u = 0; u < 4; ++u) T[(I + rr + q) + (int64_t)(J + cc + u) * ldt] -= c[q][u];
+    for (int q = 0; q < 16; ++q) {
+        const int i = 32 * wr + 8 * (q >> 2) + 4 * lh + (q & 3);
+        T[(I + i) + (int64_t)(J + 32 * wc + lr) * ldt] -= acc[q];
+    }
 }
 
 // ============================================================== strip TRSMs + rounding
@@ -257,10 +308,6 @@ constexpr int SR = 32;  // rows (columns) per strip of L21 (U12) and per scale
 // column l%32.  The strip lives in LDS (pitch odd, so the 32 rows / columns
 // a fragment touches fall in distinct banks); the factor blocks stream from
 // L2 straight into operand registers along contiguous runs.
-typedef float f16v_t __attribute__((ext_vector_type(16)));
-
-MXP_DEV f16v_t mfma2(float a, float b, f16v_t c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
-
 // add the other K-half's partial results (waves 2,3 -> waves 0,1) through LDS
 MXP_DEV void khalf_reduce(f16v_t& acc, float* red, int blk, int kh, int lane) {
     if (kh == 1)
@@ -501,6 +548,35 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
 
 // ============================================================== driver
 
+// Side stream and events for the look-ahead, one set per device (default
+// stream priority; created on first use and kept for the process).
+struct Lookahead {
+    hipStream_t side = nullptr;
+    hipEvent_t ev_cross = nullptr, ev_panel = nullptr;
+};
+static Lookahead g_la[64];
+
+static hipError_t lookahead_for_device(Lookahead** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    Lookahead& L = g_la[dev];
+    if (!L.side) {
+        if ((e = hipStreamCreateWithFlags(&L.side, hipStreamNonBlocking))) return e;
+        if ((e = hipEventCreateWithFlags(&L.ev_cross, hipEventDisableTiming))) return e;
+        if ((e = hipEventCreateWithFlags(&L.ev_panel, hipEventDisableTiming))) return e;
+    }
+    *out = &L;
+    return hipSuccess;
+}
+
+// Right-looking blocked LU with look-ahead.  Per block step k the trailing
+// update is split into the "cross" part (block column k+1 and block row k+1)
+// and the rest; the panel of step k+1 (diagonal-block LU and strip TRSMs)
+// needs only the cross part, so it runs on the side stream while the main
+// stream performs the rest of the update.  Two operand sets alternate
+// between consecutive steps.
 template <int ST, int OP>
 static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
     typedef typename Store<ST>::T ST_T;
@@ -518,57 +594,120 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
                                      (int)trsm_smem(1024)))) return e;
         attr_done = true;
     }
+    Lookahead* LA = nullptr;
+    if ((e = lookahead_for_device(&LA))) return e;
     ST_T* A = (ST_T*)p.A;
     const int64_t n = p.n, lda = p.lda;
     const int nb = (int)p.nb;
     const int64_t nstrips_total = (n + SR - 1) / SR;
-    if ((e = fill_u64(p.info, 1, ~0ull, s))) return e;
-    for (int64_t k = 0; k < n; k += nb) {
+    const int64_t opset = p.op_rows * nb;            // elements of one operand buffer
+    const int64_t scset = p.op_rows / 32;             // entries of one scale array
+
+    // diagonal-block LU of block k (latency-bound: a handful of small grids)
+    auto diag = [&](int64_t k, hipStream_t st) -> hipError_t {
         const int kb = (int)(n - k < nb ? n - k : nb);
         const int kbp = (int)rup(kb, 64);
-        const int64_t m = n - k - kb;
         const int64_t blk = k / nb;
         float* T = p.T + blk * nb * nb;
         float* linv = p.linv + blk * nb * 64;
         float* uinv = p.uinv + blk * nb * 64;
-        prof::begin(s);
-        k_diag_load<ST><<<dim3(1, kbp), 256, 0, s>>>(A, lda, k, kb, kbp, T, nb);
+        hipEvent_t pt = prof::begin(st);
+        k_diag_load<ST><<<dim3(1, kbp), 256, 0, st>>>(A, lda, k, kb, kbp, T, nb);
         for (int sb = 0; sb < kbp; sb += 64) {
-            k_leaf_lu<<<1, 256, 0, s>>>(T, nb, sb, linv + (sb / 64) * 4096, uinv + (sb / 64) * 4096, p.info, k);
+            k_leaf_lu<<<1, LEAF_THREADS, 0, st>>>(T, nb, sb, linv + (sb / 64) * 4096, uinv + (sb / 64) * 4096,
+                                                  p.info, k);
             if (sb + 64 < kbp) {
                 int R = (kbp - sb - 64) / 64;
-                k_inner_trsm<<<2 * R, 256, 0, s>>>(T, nb, sb, kbp, linv + (sb / 64) * 4096, uinv + (sb / 64) * 4096);
-                k_inner_update<<<R * R, 256, 0, s>>>(T, nb, sb, kbp);
+                k_inner_trsm<<<2 * R, 256, 0, st>>>(T, nb, sb, kbp, linv + (sb / 64) * 4096, uinv + (sb / 64) * 4096);
+                k_inner_update<<<R * R, 256, 0, st>>>(T, nb, sb, kbp);
             }
         }
-        k_diag_store<ST><<<dim3(kbp / 64, kbp / 64), 256, 0, s>>>(A, lda, k, kb, kbp, T, p.Trm + blk * nb * nb, nb);
-        prof::end(prof::DIAG, s, 2.0 / 3.0 * kb * (double)kb * kb, 2.0 * kb * (double)kb * sizeof(ST_T));
-        if ((e = hipGetLastError())) return e;
-        if (m > 0) {
-            const int nstrip = (int)(rup(m, 256) / SR);
-            const size_t smem = trsm_smem(nb);
-            prof::begin(s);
-            k_trsm_L<ST, OP><<<nstrip, 256, smem, s>>>(A, lda, n, k, nb, p.Trm + blk * nb * nb, uinv, (OP_T*)p.Lq, p.inv_sa,
-                                                       p.lsc + blk * nstrips_total);
-            k_trsm_U<ST, OP><<<nstrip, 256, smem, s>>>(A, lda, n, k, nb, T, linv, (OP_T*)p.Uq, p.inv_sb);
-            prof::end(prof::TRSM, s, 2.0 * m * (double)nb * nb,
-                      4.0 * m * (double)nb * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
-            prof::begin(s);
-            ST_T* C = A + (k + kb) + (k + kb) * lda;
-            if ((e = gemm_update(OP, ST, C, lda, m, m, nb, p.Lq, p.Uq, p.inv_sa, p.inv_sb, s))) return e;
-            prof::end(prof::GEMM, s, 2.0 * m * (double)m * nb,
-                      2.0 * m * (double)m * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
-            if ((e = hipGetLastError())) return e;
+        k_diag_store<ST><<<dim3(kbp / 64, kbp / 64), 256, 0, st>>>(A, lda, k, kb, kbp, T, p.Trm + blk * nb * nb, nb);
+        prof::end(pt, prof::DIAG, st, 2.0 / 3.0 * kb * (double)kb * kb, 2.0 * kb * (double)kb * sizeof(ST_T));
+        return hipGetLastError();
+    };
+    // strip TRSMs of block k (wide grids: all CUs)
+    auto trsm = [&](int64_t k, hipStream_t st) -> hipError_t {
+        const int kb = (int)(n - k < nb ? n - k : nb);
+        const int64_t m = n - k - kb;
+        if (m <= 0) return hipSuccess;
+        const int64_t blk = k / nb;
+        const int set = (int)(blk & 1);
+        const int nstrip = (int)(rup(m, 256) / SR);
+        const size_t smem = trsm_smem(nb);
+        hipEvent_t pt = prof::begin(st);
+        k_trsm_L<ST, OP><<<nstrip, 256, smem, st>>>(A, lda, n, k, nb, p.Trm + blk * nb * nb,
+                                                    p.uinv + blk * nb * 64, (OP_T*)p.Lq + set * opset,
+                                                    p.inv_sa + set * scset, p.lsc + blk * nstrips_total);
+        k_trsm_U<ST, OP><<<nstrip, 256, smem, st>>>(A, lda, n, k, nb, p.T + blk * nb * nb, p.linv + blk * nb * 64,
+                                                    (OP_T*)p.Uq + set * opset, p.inv_sb + set * scset);
+        prof::end(pt, prof::TRSM, st, 2.0 * m * (double)nb * nb,
+                  4.0 * m * (double)nb * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
+        return hipGetLastError();
+    };
+    // part: 0 = the whole trailing matrix, 1 = block column and block row k+1, 2 = the rest
+    auto update = [&](int64_t k, int part, hipStream_t st) -> hipError_t {
+        const int64_t m = n - k - nb;
+        const int set = (int)((k / nb) & 1);
+        const OP_T* Lq = (const OP_T*)p.Lq + set * opset;
+        const OP_T* Uq = (const OP_T*)p.Uq + set * opset;
+        const float* sa = p.inv_sa + set * scset;
+        const float* sb = p.inv_sb + set * scset;
+        ST_T* C = A + (k + nb) + (k + nb) * lda;
+        const int64_t c = nb;                       // width of block column / row k+1
+        hipEvent_t pt = prof::begin(st);
+        hipError_t e2 = hipSuccess;
+        double fl = 0, by = 0;
+        if (part == 0) {
+            e2 = gemm_update(OP, ST, C, lda, m, m, nb, Lq, Uq, sa, sb, st);
+            fl = 2.0 * m * (double)m * nb;
+            by = 2.0 * m * (double)m * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T);
+        } else if (part == 1) {
+            e2 = gemm_update(OP, ST, C, lda, m, c, nb, Lq, Uq, sa, sb, st);                 // block column
+            if (!e2)
+                e2 = gemm_update(OP, ST, C + c * lda, lda, c, m - c, nb, Lq, Uq + c * nb, sa, sb + c / 32, st);
+            fl = 2.0 * (2.0 * m - c) * c * nb;
+            by = 2.0 * (2.0 * m - c) * c * sizeof(ST_T) + (m + m) * (double)nb * sizeof(OP_T);
+        } else {
+            e2 = gemm_update(OP, ST, C + c + c * lda, lda, m - c, m - c, nb, Lq + c * nb, Uq + c * nb, sa + c / 32,
+                             sb + c / 32, st);
+            fl = 2.0 * (m - c) * (double)(m - c) * nb;
+            by = 2.0 * (m - c) * (double)(m - c) * sizeof(ST_T) + 2.0 * (m - c) * (double)nb * sizeof(OP_T);
+        }
+        prof::end(pt, prof::GEMM, st, fl, by);
+        return e2;
+    };
+
+    if ((e = fill_u64(p.info, 1, ~0ull, s))) return e;
+    if ((e = diag(0, s))) return e;
+    if ((e = trsm(0, s))) return e;
+    for (int64_t k = 0; k + nb < n; k += nb) {
+        const int64_t m = n - k - nb;               // trailing size after step k
+        if (m > nb) {
+            // cross part, then the next panel (diagonal block and both strip
+            // TRSMs) on the side stream while the main stream updates the rest
+            if ((e = update(k, 1, s))) return e;
+            if ((e = hipEventRecord(LA->ev_cross, s))) return e;
+            if ((e = hipStreamWaitEvent(LA->side, LA->ev_cross, 0))) return e;
+            if ((e = diag(k + nb, LA->side))) return e;
+            if ((e = trsm(k + nb, LA->side))) return e;
+            if ((e = hipEventRecord(LA->ev_panel, LA->side))) return e;
+            if ((e = update(k, 2, s))) return e;
+            if ((e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
+        } else {
+            if ((e = update(k, 0, s))) return e;
+            if ((e = diag(k + nb, s))) return e;
+            if ((e = trsm(k + nb, s))) return e;
         }
     }
     // full FP32 inverses of every diagonal block, used by the preconditioner
     {
         const int64_t nblk = (n + nb - 1) / nb;
         dim3 g((unsigned)(nb / SR), (unsigned)nblk);
-        prof::begin(s);
+        hipEvent_t pt = prof::begin(s);
         k_inv_upper<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.Trm, p.uinv, p.uinv_full);
         k_inv_lower<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.T, p.linv, p.linv_full);
-        prof::end(prof::DIAG, s, 2.0 / 3.0 * (double)n * nb * nb, 16.0 * (double)n * nb);
+        prof::end(pt, prof::DIAG, s, 2.0 / 3.0 * (double)n * nb * nb, 16.0 * (double)n * nb);
         if ((e = hipGetLastError())) return e;
     }
     return hipSuccess;

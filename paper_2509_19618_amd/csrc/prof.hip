@@ -19,7 +19,6 @@ static std::mutex g_mu;
 static bool g_on = false;
 static std::vector<hipEvent_t> g_pool;   // free events
 static std::vector<Rec> g_pending;       // recorded, not yet collected
-static hipEvent_t g_open = nullptr;      // start event of the launch in flight
 static double g_ms[NCLS], g_flops[NCLS], g_bytes[NCLS];
 static int64_t g_count[NCLS];
 
@@ -36,22 +35,21 @@ static hipEvent_t take() {
 
 bool enabled() { return g_on; }
 
-void begin(hipStream_t s) {
-    if (!g_on) return;
+hipEvent_t begin(hipStream_t s) {
+    if (!g_on) return nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
-    g_open = take();
-    if (g_open) hipEventRecord(g_open, s);
+    hipEvent_t a = take();
+    if (a) hipEventRecord(a, s);
+    return a;
 }
 
-void end(Cls c, hipStream_t s, double flops, double bytes) {
-    if (!g_on) return;
+void end(hipEvent_t a, Cls c, hipStream_t s, double flops, double bytes) {
+    if (!g_on || !a) return;
     std::lock_guard<std::mutex> lk(g_mu);
-    if (!g_open) return;
     hipEvent_t b = take();
-    if (!b) return;
+    if (!b) { g_pool.push_back(a); return; }
     hipEventRecord(b, s);
-    g_pending.push_back({(int)c, g_open, b, flops, bytes});
-    g_open = nullptr;
+    g_pending.push_back({(int)c, a, b, flops, bytes});
 }
 
 }  // namespace prof

@@ -110,7 +110,7 @@ static hipError_t prec_typed(const PrecPlan& p, const double* V, int64_t ldv, do
     double* R = W;                 // right-hand side, updated by the panels
     double* Y = W + n * nr;        // forward result, then the backward right-hand side
     unsigned rows_g = (unsigned)((n + 255) / 256);
-    prof::begin(s);
+    hipEvent_t pt = prof::begin(s);
     k_scale_rows<<<rows_g, 256, 0, s>>>(n, p.rowscale, V, ldv, R, nr);
     for (int64_t b = 0; b < nblk; ++b) {         // L y = S v
         int64_t k = b * nb;
@@ -132,7 +132,7 @@ static hipError_t prec_typed(const PrecPlan& p, const double* V, int64_t ldv, do
                                                                                         p.lda, nullptr, R, Y);
     }
     k_copy_cols<<<rows_g, 256, 0, s>>>(n, R, Z, ldz, nr);
-    prof::end(prof::PREC, s, 2.0 * n * (double)n * nr, (double)n * n * sizeof(T) + 8.0 * n * nb);
+    prof::end(pt, prof::PREC, s, 2.0 * n * (double)n * nr, (double)n * n * sizeof(T) + 8.0 * n * nb);
     return hipGetLastError();
 }
 
