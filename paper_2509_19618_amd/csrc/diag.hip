@@ -1,0 +1,418 @@
+// diag.hip -- FP32 LU without pivoting of one diagonal block, in a single
+// work-group (the panel factorisation of the right-looking blocked LU,
+// Section 3 "HPL-MxP": the diagonal block is factored in 32-bit arithmetic
+// before the 16-bit trailing update).
+//
+// The block is at most 1024 x 1024 and its factorisation is a chain of small
+// dependent steps, so one work-group of eight waves owns it from start to
+// end: no launch gaps, no competition with the trailing update for the
+// dispatcher, and every intermediate result stays in the CU's L1/LDS or the
+// XCD's L2.  The block is copied to an FP32 workspace T (column-major,
+// ld = ldt) and factored right-looking over 32 x 32 tiles:
+//
+//   for t = 0 .. P-1   (P = kbp / 32)
+//     phase L: waves 0 and 1 each apply the last update to tile (t,t) and
+//              factor it in registers (row r of the tile in lane r); wave 0
+//              then forms the inverse of its unit-lower factor, wave 1 that
+//              of its upper factor.  Waves 2..7 (and 0, 1 once done) apply
+//              update t-1 to every other trailing tile.
+//     phase T: tiles (i,t) <- tile(i,t) U_tt^-1 and (t,j) <- L_tt^-1 tile(t,j)
+//
+// Every 32 x 32 x 32 product is one wave's chain of sixteen
+// v_mfma_f32_32x32x2f32.  The kernel also writes the inverses of the 64 x 64
+// unit-lower (column-major) and upper (row-major) diagonal sub-blocks used by
+// the strip TRSMs, the factored block back into A in the storage format, and
+// a row-major copy Trm of T.
+#include <type_traits>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace mxp {
+
+namespace {
+
+typedef float f16v_t __attribute__((ext_vector_type(16)));
+typedef float v32f __attribute__((ext_vector_type(32)));
+
+constexpr int DW = 8;              // waves of the work-group
+constexpr int DT = DW * 64;        // threads
+constexpr int TP = 33;             // LDS pitch of a staged 32 x 32 tile (column-major)
+constexpr int TILE_F = 32 * TP;    // floats of one staged tile
+
+// v, hidden from the optimiser (keeps loop-invariant per-lane constants
+// from being hoisted out of the block loop and held in registers throughout)
+MXP_DEV int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+MXP_DEV float rl(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
+
+// s[c*TP + r] = g[r + c*ld] for r, c < 32 (lanes along r: coalesced)
+MXP_DEV void stage_cm(float* s, const float* g, int64_t ld) {
+    const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = g[(int64_t)(2 * q) * ld + (r + h * (int)ld)];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s[(2 * q + h) * TP + r] = v[q];
+}
+
+// s[c*TP + r] = g[r*ld + c] for r, c < 32 (lanes along c: coalesced)
+MXP_DEV void stage_rm(float* s, const float* g, int64_t ld) {
+    const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
+    float v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) v[q] = g[(int64_t)(2 * q) * ld + (c + h * (int)ld)];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) s[c * TP + 2 * q + h] = v[q];
+}
+
+// Product R = P Q of two 32 x 32 operands.  On return register q of lane l
+// holds R[l % 32][cc(q, l)], cc = 8(q/4) + 4(l/32) + q%4: the MFMA computes
+// R^T = Q^T P^T, so that a result column is spread over 32 consecutive lanes
+// and is written with one coalesced access.  With r = l % 32 and
+// k = 2 k2 + l / 32, fp(k2) = P[r][k] and fq(k2) = Q[k][r]; the fetchers
+// split their addresses into a uniform part (depending on k2 only) and one
+// 32-bit lane offset, which keeps the sixteen loads in two registers.
+template <class FP, class FQ>
+MXP_DEV f16v_t prod32(FP fp, FQ fq) {
+    float a[16], b[16];
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) {
+        b[k2] = fq(k2);
+        a[k2] = fp(k2);
+    }
+    f16v_t acc = {};
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(b[k2], a[k2], acc, 0, 0, 0);
+    return acc;
+}
+
+MXP_DEV int res_col(int q, int lh) { return 8 * (q >> 2) + 4 * lh + (q & 3); }
+// uniform part of res_col
+MXP_DEV int res_colu(int q) { return 8 * (q >> 2) + (q & 3); }
+
+}  // namespace
+
+template <int ST>
+__global__ __launch_bounds__(DT) void k_diag_lu(typename Store<ST>::T* A, int64_t lda, int64_t k, int kb, int kbp,
+                                                float* __restrict__ T, float* __restrict__ Trm, int ldt,
+                                                float* __restrict__ linv, float* __restrict__ uinv,
+                                                unsigned long long* info) {
+    extern __shared__ __attribute__((aligned(16))) float dsm[];
+    __shared__ int s_cnt[2];
+    const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lr = lane & 31, lh = lane >> 5;
+    float* sA = dsm + (2 * wave) * TILE_F;       // two staging tiles per wave
+    float* sB = sA + TILE_F;
+    float* sLinv = dsm + 2 * DW * TILE_F;        // inverses of the current tile's factors
+    float* sUinv = sLinv + TILE_F;
+    const int P = kbp / 32;
+    auto Tt = [&](int I, int J) -> float* { return T + 32 * I + (int64_t)(32 * J) * ldt; };
+    const int offA = lr + lh * ldt;          // lane offset of operand element (lr, 2 k2 + lh) of a T tile
+    const int offC = lr + 4 * lh * ldt;      // lane offset of result element (lr, res_col(q))
+    // operand fetchers: P[lr][k] of a T tile, P and Q of a staged LDS tile
+    auto gP = [&](const float* G) { return [=](int k2) { return G[(int64_t)(2 * k2) * ldt + offA]; }; };
+    auto sP = [&](const float* S) { return [=](int k2) { return S[(2 * k2 + lh) * TP + lr]; }; };
+    auto sQ = [&](const float* S) { return [=](int k2) { return S[lr * TP + 2 * k2 + lh]; }; };
+    auto Cp = [&](float* G, int q) -> float& { return G[(int64_t)res_colu(q) * ldt + offC]; };
+    // a final tile (I,J), held column-major in the LDS buffer S: to A in the
+    // storage format and, transposed, to Trm (both with coalesced stores)
+    auto store_final = [&](int I, int J, const float* S) {
+        const int i = 32 * I + lr;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = 32 * J + 2 * q + lh;
+            if (i < kb && j < kb) A[(k + i) + (k + j) * lda] = Store<ST>::from_f32(S[(2 * q + lh) * TP + lr]);
+            Trm[(32 * J + lr) + (int64_t)(32 * I + 2 * q + lh) * ldt] = S[lr * TP + 2 * q + lh];
+        }
+    };
+    auto claim = [&](int which) -> int {
+        int v = 0;
+        if (lane == 0) v = atomicAdd(&s_cnt[which], 1);
+        return __builtin_amdgcn_readfirstlane(v);
+    };
+
+    // ---- load: T <- A11 in FP32, padded with the identity (branch-free, so
+    // that the loads of a tile are all in flight together)
+    if (tid == 0) s_cnt[0] = s_cnt[1] = 0;
+    for (int u = wave; u < P * P; u += DW) {
+        const int I = u % P, J = u / P;
+        const int i = 32 * I + lr;
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int j = 32 * J + 2 * q + lh;
+            const bool in = i < kb && j < kb;
+            v[q] = Store<ST>::load(A, in ? (k + i) + (k + j) * lda : k + k * lda);
+            v[q] = in ? v[q] : ((i == j) ? 1.0f : 0.0f);
+        }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) T[i + (int64_t)(32 * J + 2 * q + lh) * ldt] = v[q];
+    }
+    __syncthreads();
+
+    for (int t = 0; t < P; ++t) {
+        // ================= phase L(t)
+        if (wave < 2) {
+            // tile (t,t) after the last update, into sA (column-major, pitch TP)
+            if (t == 0) {
+                stage_cm(sA, Tt(0, 0), ldt);
+            } else {
+                stage_cm(sB, Tt(t - 1, t), ldt);
+                const float* Lg = Tt(t, t - 1);
+                const f16v_t acc = prod32(gP(Lg), sQ(sB));
+                float* Cg = Tt(t, t);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = Cp(Cg, q) - acc[q];
+            }
+            // LU in registers: lane r (and r + 32) holds row r.  The step loop
+            // stays rolled (small code: the kernel runs once per block, its
+            // instruction cache cold); the step's own column is read through
+            // the register index (s_set_gpr_idx).  Every step sweeps all 32
+            // columns of the rows below the pivot: left of the diagonal a row
+            // then holds junk, never read again, and the multipliers go to sA
+            // (column j of L).
+            v32f x;
+#pragma unroll
+            for (int c = 0; c < 32; ++c) x[c] = sA[c * TP + lr];
+            float dinv = 0.0f;   // lane j: 1 / U[j][j]
+            // step j; columns left of C0 are left alone (junk for j >= C0)
+            auto lu_step = [&](int j, auto C0) {
+                const float xj = x[j];
+                const float rp = 1.0f / rl(xj, j);
+                dinv = (lr == j) ? rp : dinv;
+                if (lr > j) {
+                    // rows at or above the pivot stay as they are (readlane
+                    // reads the pivot lane whatever the execution mask)
+                    const float l = xj * rp;
+#pragma unroll
+                    for (int c = decltype(C0)::value; c < 32; ++c) x[c] = fmaf(-l, rl(x[c], j), x[c]);
+                    if (lh == 0) sA[j * TP + lr] = l;
+                }
+            };
+#pragma unroll 1
+            for (int j = 0; j < 16; ++j) lu_step(j, std::integral_constant<int, 0>());
+#pragma unroll 1
+            for (int j = 16; j < 31; ++j) lu_step(j, std::integral_constant<int, 16>());
+            dinv = (lr == 31) ? 1.0f / rl(x[31], 31) : dinv;
+            const int o = 32 * (t & 1);
+            float* L64 = linv + (t >> 1) * 4096;   // column-major 64 x 64
+            float* U64 = uinv + (t >> 1) * 4096;   // row-major 64 x 64
+            float X[32];
+            const int lro = opaque(lr);
+#pragma unroll
+            for (int c = 0; c < 32; ++c) X[c] = (c == lro) ? 1.0f : 0.0f;
+            if (wave == 0) {
+                float* Cg = Tt(t, t);
+                if (lh == 0) {
+#pragma unroll
+                    for (int c = 0; c < 32; ++c) {
+                        const float f = (c >= lr) ? x[c] : sA[c * TP + lr];
+                        Cg[lr + (int64_t)c * ldt] = f;
+                        sB[c * TP + lr] = f;
+                    }
+                }
+                store_final(t, t, sB);
+                // the pivots are the diagonal of U: report the first zero / non-finite one
+                int bad = -1;
+#pragma unroll
+                for (int c = 31; c >= 0; --c) {
+                    const float d = rl(x[c], c);
+                    if (32 * t + c < kb && !(d != 0.0f && isfinite(d))) bad = c;
+                }
+                if (bad >= 0 && lane == 0) atomicMin(info, (unsigned long long)(k + 32 * t + bad + 1));
+                // L^-1 by rows: X[i] = e_i - sum_{s<i} L[i][s] X[s]
+                // (row s of X is zero right of s: the sweep stops at C1)
+                auto linv_step = [&](int s2, auto C1) {
+                    if (lr > s2) {
+                        const float l = sA[s2 * TP + lr];
+#pragma unroll
+                        for (int c = 0; c < decltype(C1)::value; ++c) X[c] = fmaf(-l, rl(X[c], s2), X[c]);
+                    }
+                };
+#pragma unroll 1
+                for (int s2 = 0; s2 < 16; ++s2) linv_step(s2, std::integral_constant<int, 16>());
+#pragma unroll 1
+                for (int s2 = 16; s2 < 31; ++s2) linv_step(s2, std::integral_constant<int, 32>());
+                if (lh == 0) {
+#pragma unroll
+                    for (int c = 0; c < 32; ++c) {
+                        sLinv[c * TP + lr] = X[c];
+                        L64[(o + lr) + 64 * (o + c)] = X[c];
+                        if (o == 0) L64[lr + 64 * (32 + c)] = 0.0f;
+                    }
+                }
+            } else {
+                // U^-1 by rows, last row first: X[i] = (e_i - sum_{s>i} U[i][s] X[s]) / U[i][i]
+                // (row s of X is zero left of s: the sweep starts at C0)
+                auto uinv_step = [&](int s2, auto C0) {
+                    const float sc = (lr == s2) ? dinv : 1.0f;
+#pragma unroll
+                    for (int c = decltype(C0)::value; c < 32; ++c) X[c] *= sc;
+                    const float w = x[s2];
+                    if (lr < s2) {
+#pragma unroll
+                        for (int c = decltype(C0)::value; c < 32; ++c) X[c] = fmaf(-w, rl(X[c], s2), X[c]);
+                    }
+                };
+#pragma unroll 1
+                for (int s2 = 31; s2 >= 16; --s2) uinv_step(s2, std::integral_constant<int, 16>());
+#pragma unroll 1
+                for (int s2 = 15; s2 >= 0; --s2) uinv_step(s2, std::integral_constant<int, 0>());
+                if (lh == 0) {
+#pragma unroll
+                    for (int c = 0; c < 32; ++c) sUinv[c * TP + lr] = X[c];
+                }
+                // row-major copy, read back transposed so that the global stores coalesce
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int r = 2 * q + lh;
+                    U64[64 * (o + r) + o + lr] = sUinv[lr * TP + r];
+                    if (o == 32) U64[64 * (32 + r) + lr] = 0.0f;
+                }
+            }
+        }
+        if (t > 0) {
+            // update t-1 of every trailing tile except (t,t), two tiles per
+            // claim with all their global loads in flight at once
+            const int w = P - t, ntask = w * w - 1;
+            float v[2][16], a[2][16], cv[2][16];
+            for (;;) {
+                const int u = 2 * claim(0);
+                if (u >= ntask) break;
+                const int nt = (u + 1 < ntask) ? 2 : 1;
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    if (e < nt) {
+                        const int i = t + (u + e + 1) % w, j = t + (u + e + 1) / w;
+                        const float* Ug = Tt(t - 1, j);
+                        const float* Lg = Tt(i, t - 1);
+                        float* Cg = Tt(i, j);
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) v[e][q] = Ug[(int64_t)(2 * q) * ldt + offA];
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) a[e][q] = Lg[(int64_t)(2 * q) * ldt + offA];
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) cv[e][q] = Cp(Cg, q);
+                    }
+                }
+#pragma unroll
+                for (int e = 0; e < 2; ++e) {
+                    if (e < nt) {
+                        const int i = t + (u + e + 1) % w, j = t + (u + e + 1) / w;
+                        float* Cg = Tt(i, j);
+                        float* S = e ? sB : sA;
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) S[(2 * q + lh) * TP + lr] = v[e][q];
+                        const f16v_t acc = prod32([&](int k2) { return a[e][k2]; }, sQ(S));
+#pragma unroll
+                        for (int q = 0; q < 16; ++q) Cp(Cg, q) = cv[e][q] - acc[q];
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_cnt[0] = 0;
+        // ================= phase T(t)
+        {
+            const int w = P - 1 - t;
+            for (;;) {
+                const int u = claim(1);
+                if (u >= 2 * w) break;
+                if (u < w) {
+                    // tile (i,t) <- tile (i,t) U_tt^-1
+                    float* Xg = Tt(t + 1 + u, t);
+                    const f16v_t acc = prod32(gP(Xg), sQ(sUinv));
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        Cp(Xg, q) = acc[q];
+                        sB[res_col(q, lh) * TP + lr] = acc[q];
+                    }
+                    store_final(t + 1 + u, t, sB);
+                } else {
+                    // tile (t,j) <- L_tt^-1 tile (t,j)
+                    float* Yg = Tt(t, t + 1 + (u - w));
+                    stage_cm(sA, Yg, ldt);
+                    const f16v_t acc = prod32(sP(sLinv), sQ(sA));
+#pragma unroll
+                    for (int q = 0; q < 16; ++q) {
+                        Cp(Yg, q) = acc[q];
+                        sB[res_col(q, lh) * TP + lr] = acc[q];
+                    }
+                    store_final(t, t + 1 + (u - w), sB);
+                }
+            }
+        }
+        __syncthreads();
+        if (tid == 0) s_cnt[1] = 0;
+    }
+
+    // ---- off-diagonal blocks of the 64 x 64 inverses
+    for (int u = wave; u < P; u += DW) {
+        if (u < P / 2) {
+            // [L11 0; L21 L22]^-1 = [L11^-1 0; -L22^-1 L21 L11^-1  L22^-1]
+            const int b = u;
+            float* L64 = linv + b * 4096;
+            const float* L21 = Tt(2 * b + 1, 2 * b);
+            stage_cm(sA, L64, 64);
+            const f16v_t y = prod32(gP(L21), sQ(sA));
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = y[q];
+            const float* L22i = L64 + 32 + 64 * 32;
+            const f16v_t x = prod32([=](int k2) { return L22i[128 * k2 + lr + 64 * lh]; }, sQ(sA));
+#pragma unroll
+            for (int q = 0; q < 16; ++q) L64[(32 + lr) + 64 * res_col(q, lh)] = -x[q];
+        } else {
+            // [U11 U12; 0 U22]^-1 = [U11^-1  -U11^-1 U12 U22^-1; 0 U22^-1]
+            const int b = u - P / 2;
+            float* U64 = uinv + b * 4096;
+            const float* U12 = Tt(2 * b, 2 * b + 1);
+            const float* U22i = U64 + 64 * 32 + 32;
+            const f16v_t z = prod32(gP(U12), [=](int k2) { return U22i[128 * k2 + 64 * lh + lr]; });
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sB[res_col(q, lh) * TP + lr] = z[q];
+            stage_rm(sA, U64, 64);
+            const f16v_t x = prod32(sP(sA), sQ(sB));
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = -x[q];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int r = 2 * q + lh;
+                U64[64 * r + 32 + lr] = sA[lr * TP + r];
+            }
+        }
+    }
+}
+
+size_t diag_lu_smem() { return (size_t)(2 * DW + 2) * TILE_F * sizeof(float); }
+
+template <int ST>
+static hipError_t diag_lu_typed(void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
+                                float* linv, float* uinv, unsigned long long* info, hipStream_t s) {
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void*)k_diag_lu<ST>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)diag_lu_smem());
+        if (e) return e;
+        attr_done = true;
+    }
+    k_diag_lu<ST><<<1, DT, diag_lu_smem(), s>>>((typename Store<ST>::T*)A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv,
+                                                info);
+    return hipGetLastError();
+}
+
+hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
+                   float* linv, float* uinv, unsigned long long* info, hipStream_t s) {
+    if (kb < 1 || kbp % 64 || kbp > ldt || kb > kbp) return hipErrorInvalidValue;
+    switch (store) {
+    case F32: return diag_lu_typed<F32>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, info, s);
+    case F16: return diag_lu_typed<F16>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, info, s);
+    case BF16: return diag_lu_typed<BF16>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, info, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace mxp

@@ -51,10 +51,14 @@ int64_t operand_rows(int64_t n);
 WorkLayout work_layout(int64_t n, int64_t nb, int update);
 int dtype_bytes(int dt);
 
-// CUs the trailing update leaves free (set around the look-ahead steps)
 // C (M x N, storage) <- C - diag(inv_sa) Aq Bq^T diag(inv_sb); Aq/Bq rows padded to 256
 hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq,
                        const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s);
+// FP32 LU of the diagonal block A[k:k+kb, k:k+kb] (padded to kbp, a multiple
+// of 64, with the identity) in one work-group: T/Trm (ld ldt) get L\U column-
+// and row-major, linv/uinv the 64x64 sub-block inverses, A the factored block.
+hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
+                   float* linv, float* uinv, unsigned long long* info, hipStream_t s);
 hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t s);
 hipError_t factor_run(const FactorPlan& p, hipStream_t s);
 

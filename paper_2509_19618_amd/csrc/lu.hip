@@ -5,8 +5,9 @@
 // the input allowed).
 //
 // Per block step k (block size nb):
-//   1. diagonal block A11 -> FP32, LU in FP32 with 64-wide inner blocking;
-//      inverses of the 64x64 diagonal sub-blocks of L11 and U11 kept;
+//   1. diagonal block A11 -> FP32, LU in FP32 by one work-group over 32x32
+//      tiles (diag.hip); inverses of the 64x64 diagonal sub-blocks of L11
+//      and U11 kept;
 //   2. L21 = A21 U11^-1 and U12 = L11^-1 A12 by blocked substitution in
 //      FP32, one workgroup per 32-row (32-column) strip, fused with the
 //      rounding to the update format under a power-of-two strip scale;
@@ -104,202 +105,10 @@ hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t 
     return hipGetLastError();
 }
 
-// ============================================================== diagonal block
-// T (FP32, ld = nb) <- A11, padded to a multiple of 64 with the identity.
-template <int ST>
-__global__ __launch_bounds__(256) void k_diag_load(const typename Store<ST>::T* A, int64_t lda, int64_t k, int kb,
-                                                   int kbp, float* T, int ldt) {
-    int j = blockIdx.y;
-    for (int i = threadIdx.x; i < kbp; i += 256) {
-        float v;
-        if (i < kb && j < kb) v = Store<ST>::load(A, (k + i) + (k + j) * lda);
-        else v = (i == j) ? 1.0f : 0.0f;
-        T[i + (int64_t)j * ldt] = v;
-    }
-}
-
-// A11 (storage format) <- T (FP32 L11\U11); Trm <- T transposed (row-major
-// copy: rows of U11 contiguous), padded part included.
-template <int ST>
-__global__ __launch_bounds__(256) void k_diag_store(typename Store<ST>::T* A, int64_t lda, int64_t k, int kb, int kbp,
-                                                    const float* T, float* Trm, int ldt) {
-    __shared__ float tile[64][65];
-    const int i0 = blockIdx.x * 64, j0 = blockIdx.y * 64;
-    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;
-    for (int c = g; c < 64; c += 4) {
-        const float v = T[(i0 + r) + (int64_t)(j0 + c) * ldt];
-        tile[r][c] = v;
-        if (i0 + r < kb && j0 + c < kb) A[(k + i0 + r) + (k + j0 + c) * lda] = Store<ST>::from_f32(v);
-    }
-    __syncthreads();
-    for (int c = g; c < 64; c += 4) Trm[(j0 + r) + (int64_t)(i0 + c) * ldt] = tile[c][r];
-}
-
-// LU of the 64x64 tile T[s:s+64, s:s+64], then the inverses of its
-// unit-lower and upper factors.  1024 threads: thread (r, g) keeps row r,
-// columns g, g+16, g+32, g+48 in registers; each elimination step
-// broadcasts the pivot row and column through LDS (two buffers alternate,
-// so one barrier per step suffices).  Sixteen waves keep the four SIMDs
-// busy across the short dependent chain of every step.  L^-1 is stored
-// column-major and U^-1 row-major: both are then read along contiguous runs
-// by the MFMA operand loads of the strip solves.  A zero or non-finite pivot
-// records its 1-based global column in *info (atomic min).
-constexpr int LEAF_THREADS = 1024;
-__global__ __launch_bounds__(LEAF_THREADS) void k_leaf_lu(float* T, int ldt, int s, float* linv, float* uinv,
-                                                          unsigned long long* info, int64_t col0) {
-    __shared__ float a[64][65];
-    __shared__ float rowb[2][64], colb[2][64];
-    __shared__ float rl[2][64], ru[2][64];
-    const int tid = threadIdx.x, r = tid & 63, g = tid >> 6;   // g in 0..15
-    float v[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = T[(s + r) + (int64_t)(s + g + 16 * t) * ldt];
-#pragma unroll 1
-    for (int j = 0; j < 64; ++j) {
-        const int b = j & 1, jt = j >> 4;
-        const float vj = (jt == 0) ? v[0] : (jt == 1) ? v[1] : (jt == 2) ? v[2] : v[3];
-        if (g == (j & 15)) colb[b][r] = vj;
-        if (r == j) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) rowb[b][g + 16 * t] = v[t];
-        }
-        __syncthreads();
-        const float rp = 1.0f / rowb[b][j];
-        if (r > j) {
-            const float l = colb[b][r] * rp;
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const int c = g + 16 * t;
-                const float upd = v[t] - l * rowb[b][c];
-                v[t] = (c > j) ? upd : ((c == j) ? l : v[t]);
-            }
-        }
-    }
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int c = g + 16 * t;
-        T[(s + r) + (int64_t)(s + c) * ldt] = v[t];
-        a[r][c] = v[t];
-        // the pivots are the final diagonal of U: report the first zero / non-finite one
-        if (c == r && (v[t] == 0.0f || !isfinite(v[t]))) atomicMin(info, (unsigned long long)(col0 + s + r + 1));
-    }
-    __syncthreads();
-    // L^-1: X = I; for t ascending, rows i > t: X[i][:] -= L[i][t] X[t][:]
-    // U^-1: X = I; for t descending: X[t][:] /= U[t][t]; rows i < t: X[i][:] -= U[i][t] X[t][:]
-    float xl[4], xu[4];
-#pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        xl[t] = (r == g + 16 * t) ? 1.0f : 0.0f;
-        xu[t] = xl[t];
-    }
-#pragma unroll 1
-    for (int q = 0; q < 64; ++q) {
-        const int t = q, tu = 63 - q, b = q & 1;
-        if (r == t) {
-#pragma unroll
-            for (int u = 0; u < 4; ++u) rl[b][g + 16 * u] = xl[u];
-        }
-        if (r == tu) {
-            const float d = a[tu][tu];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                xu[u] = xu[u] / d;
-                ru[b][g + 16 * u] = xu[u];
-            }
-        }
-        __syncthreads();
-        if (r > t) {
-            const float l = a[r][t];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) xl[u] -= l * rl[b][g + 16 * u];
-        }
-        if (r < tu) {
-            const float w = a[r][tu];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) xu[u] -= w * ru[b][g + 16 * u];
-        }
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int c = g + 16 * u;
-        linv[r + 64 * c] = xl[u];   // column-major
-        uinv[64 * r + c] = xu[u];   // row-major
-    }
-}
-
+// ============================================================== strip TRSMs + rounding
 typedef float f16v_t __attribute__((ext_vector_type(16)));
 MXP_DEV f16v_t mfma2(float a, float b, f16v_t c) { return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0); }
 
-// Inner step s of the diagonal-block LU, on the FP32 matrix cores.  Four
-// waves, each a 32x32 block of a 64x64 tile (MFMA 32x32x2: lane l holds
-// A[l%32][k0 + l/32], B[k0 + l/32][l%32]; register q of the result is row
-// 8(q/4) + 4(l/32) + q%4, column l%32).
-//   trsm:   T[I, s] <- T[I, s] Uinv_s (I > s) and T[s, J] <- Linv_s T[s, J] (J > s)
-//   update: T[I, J] -= T[I, s] T[s, J]  (I, J > s)
-__global__ __launch_bounds__(256) void k_inner_trsm(float* T, int ldt, int s, int kbp, const float* linv,
-                                                    const float* uinv) {
-    __shared__ float sB[64][65];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 31, lh = lane >> 5, wr = wave & 1, wc = wave >> 1;
-    const int R = (kbp - s - 64) / 64;
-    const int w = blockIdx.x;
-    const bool lower = w < R;
-    const int t = s + 64 + 64 * (lower ? w : w - R);
-    const int64_t r0 = lower ? t : s, c0 = lower ? s : t;
-    f16v_t acc = {};
-    if (lower) {
-        // X (rows t.., cols s..) times Uinv (row-major): A from T, B from uinv, both read along contiguous runs
-#pragma unroll 8
-        for (int k2 = 0; k2 < 32; ++k2) {
-            const int k = 2 * k2 + lh;
-            acc = mfma2(T[(r0 + 32 * wr + lr) + (c0 + k) * ldt], uinv[k * 64 + 32 * wc + lr], acc);
-        }
-    } else {
-        // Linv (column-major) times X (rows s.., cols t..): X staged through LDS
-        for (int e = tid; e < 4096; e += 256) {
-            int i = e & 63, j = e >> 6;
-            sB[i][j] = T[(r0 + i) + (c0 + j) * ldt];
-        }
-        __syncthreads();
-#pragma unroll 8
-        for (int k2 = 0; k2 < 32; ++k2) {
-            const int k = 2 * k2 + lh;
-            acc = mfma2(linv[(32 * wr + lr) + 64 * k], sB[k][32 * wc + lr], acc);
-        }
-    }
-    __syncthreads();   // every wave has read the block before it is overwritten
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int i = 32 * wr + 8 * (q >> 2) + 4 * lh + (q & 3);
-        T[(r0 + i) + (c0 + 32 * wc + lr) * ldt] = acc[q];
-    }
-}
-
-__global__ __launch_bounds__(256) void k_inner_update(float* T, int ldt, int s, int kbp) {
-    __shared__ float sB[64][65];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 31, lh = lane >> 5, wr = wave & 1, wc = wave >> 1;
-    const int R = (kbp - s - 64) / 64;
-    const int I = s + 64 + 64 * (blockIdx.x % R), J = s + 64 + 64 * (blockIdx.x / R);
-    for (int e = tid; e < 4096; e += 256) {
-        int i = e & 63, j = e >> 6;
-        sB[i][j] = T[(s + i) + (int64_t)(J + j) * ldt];
-    }
-    __syncthreads();
-    f16v_t acc = {};
-#pragma unroll 8
-    for (int k2 = 0; k2 < 32; ++k2) {
-        const int k = 2 * k2 + lh;
-        acc = mfma2(T[(I + 32 * wr + lr) + (int64_t)(s + k) * ldt], sB[k][32 * wc + lr], acc);
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        const int i = 32 * wr + 8 * (q >> 2) + 4 * lh + (q & 3);
-        T[(I + i) + (int64_t)(J + 32 * wc + lr) * ldt] -= acc[q];
-    }
-}
-
-// ============================================================== strip TRSMs + rounding
 constexpr int SR = 32;  // rows (columns) per strip of L21 (U12) and per scale
 
 // The strip solves run on the FP32 matrix cores (v_mfma_f32_32x32x2f32):
@@ -612,17 +421,8 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
         float* linv = p.linv + blk * nb * 64;
         float* uinv = p.uinv + blk * nb * 64;
         hipEvent_t pt = prof::begin(st);
-        k_diag_load<ST><<<dim3(1, kbp), 256, 0, st>>>(A, lda, k, kb, kbp, T, nb);
-        for (int sb = 0; sb < kbp; sb += 64) {
-            k_leaf_lu<<<1, LEAF_THREADS, 0, st>>>(T, nb, sb, linv + (sb / 64) * 4096, uinv + (sb / 64) * 4096,
-                                                  p.info, k);
-            if (sb + 64 < kbp) {
-                int R = (kbp - sb - 64) / 64;
-                k_inner_trsm<<<2 * R, 256, 0, st>>>(T, nb, sb, kbp, linv + (sb / 64) * 4096, uinv + (sb / 64) * 4096);
-                k_inner_update<<<R * R, 256, 0, st>>>(T, nb, sb, kbp);
-            }
-        }
-        k_diag_store<ST><<<dim3(kbp / 64, kbp / 64), 256, 0, st>>>(A, lda, k, kb, kbp, T, p.Trm + blk * nb * nb, nb);
+        hipError_t e2 = diag_lu(ST, A, lda, k, kb, kbp, T, p.Trm + blk * nb * nb, nb, linv, uinv, p.info, st);
+        if (e2) return e2;
         prof::end(pt, prof::DIAG, st, 2.0 / 3.0 * kb * (double)kb * kb, 2.0 * kb * (double)kb * sizeof(ST_T));
         return hipGetLastError();
     };
