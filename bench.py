@@ -17,11 +17,20 @@ Prints ONE JSON line.
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import os
 import statistics
+import subprocess
 import sys
 import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+PROFILES = os.path.join(ROOT, "profiles")
+GEMM_SRC = os.path.join(ROOT, "paper_2509_19618_amd", "csrc", "gemm.hip")
+CALIB_BYTES = 1 << 30   # size of the plain copy that calibrates the HBM byte counters
 
 PEAK = {  # MI355X published dense peaks
     "hbm_gbs": 8000.0,
@@ -43,24 +52,103 @@ def parse():
     ap.add_argument("--store", default="f16")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--cpu-n", type=int, default=3072, help="oracle sample size for the CPU baseline")
+    ap.add_argument("--cpu-n", type=int, default=4608, help="oracle sample size for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
+    ap.add_argument("--traffic-run", action="store_true",
+                    help="one untimed step plus a %d-byte calibration copy, for rocprofv3 --pmc" % CALIB_BYTES)
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="turn two rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE csv outputs into the traffic summary")
+    ap.add_argument("--summarize-stats", metavar="DIR",
+                    help="turn a rocprofv3 --kernel-trace --stats csv output into a kernel-time summary")
+    ap.add_argument("--cmd", default="", help="the rocprofv3 command(s) that produced the summarized output")
     return ap.parse_args()
 
 
+def gemm_source_hash() -> str:
+    with open(GEMM_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def traffic_file(args) -> str:
+    return os.path.join(PROFILES, "k_gemm_update_traffic_n%d_nb%d_%s_%s.txt" % (args.n, args.nb, args.update,
+                                                                               args.store))
+
+
+def _csv_rows(d: str, suffix: str):
+    rows = []
+    for fn in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(fn, newline="") as f:
+            rows.extend(csv.DictReader(f))
+    if not rows:
+        raise SystemExit("no *%s under %s" % (suffix, d))
+    return rows
+
+
+def summarize_pmc(args):
+    """HBM bytes per trailing-update launch from FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    plain copy of CALIB_BYTES at the end of the traffic run."""
+    out = {}
+    for counter, d in (("FETCH_SIZE", args.summarize_pmc[0]), ("WRITE_SIZE", args.summarize_pmc[1])):
+        rows = [r for r in _csv_rows(d, "counter_collection.csv") if r["Counter_Name"] == counter]
+        gemm = [float(r["Counter_Value"]) for r in rows if "k_gemm_update" in r["Kernel_Name"]]
+        copies = [r for r in rows if "copyBuffer" in r["Kernel_Name"] or "copy" in r["Kernel_Name"].lower()]
+        calib_kib = float(copies[-1]["Counter_Value"])       # the calibration copy is the last copy
+        factor = (CALIB_BYTES / 1024.0) / calib_kib
+        out[counter] = {"launches": len(gemm), "raw_kib_per_launch": sum(gemm) / len(gemm),
+                        "calib_raw_kib": calib_kib, "calib_factor": factor,
+                        "bytes_per_launch": sum(gemm) / len(gemm) * 1024.0 * factor}
+    rec = {"kernel": "k_gemm_update<%s,%s>" % (args.update, args.store), "gemm_source_sha256_16": gemm_source_hash(),
+           "workload": "n=%d nb=%d, one factorisation" % (args.n, args.nb),
+           "fetch_bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"],
+           "write_bytes_per_launch": out["WRITE_SIZE"]["bytes_per_launch"],
+           "traffic_bytes_per_launch": out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"],
+           "counters": out}
+    os.makedirs(PROFILES, exist_ok=True)
+    with open(traffic_file(args), "w") as f:
+        f.write("# HBM traffic of the trailing update (rocprofv3 --pmc, one counter per run)\n")
+        f.write("# command: %s\n" % args.cmd)
+        f.write("# each counter is scaled by the ratio of true to counted bytes of a %d-byte plain copy\n"
+                % CALIB_BYTES)
+        f.write(json.dumps(rec, indent=1) + "\n")
+    print(json.dumps(rec))
+
+
+def summarize_stats(args):
+    rows = _csv_rows(args.summarize_stats, "kernel_stats.csv")
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    os.makedirs(PROFILES, exist_ok=True)
+    fn = os.path.join(PROFILES, "kernel_stats_n%d_nb%d_%s_%s.txt" % (args.n, args.nb, args.update, args.store))
+    with open(fn, "w") as f:
+        f.write("# rocprofv3 --kernel-trace --stats summary, one timed bench step (n=%d nb=%d %s/%s)\n"
+                % (args.n, args.nb, args.update, args.store))
+        f.write("# command: %s\n" % args.cmd)
+        f.write("%-60s %7s %12s %12s %7s\n" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
+        for r in rows[:25]:
+            name = r["Name"].split("(")[0].replace("void ", "")[:60]
+            f.write("%-60s %7d %12.3f %12.2f %7.2f\n" % (name, int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
+                                                        float(r["AverageNs"]) / 1e3,
+                                                        100.0 * float(r["TotalDurationNs"]) / total))
+    print(open(fn).read())
+
+
 def cpu_baseline(n: int, seed: int) -> dict:
-    """The oracle (plain C, FP64, one thread) on a bounded sample of the same
-    workload: generate, unpivoted LU, GMRES-IR at size n."""
-    import oracle
-    oracle.build()
-    t0 = time.perf_counter()
-    A, B, X, reps = oracle.solve(n, seed)
-    t = time.perf_counter() - t0
-    assert reps[0]["status"] == 0 and reps[0]["eta"] < 16
+    """The oracle (plain C, FP64) on a bounded sample of the same workload:
+    generate, unpivoted LU, GMRES-IR at size n, in a child process pinned to
+    one OpenMP thread so that the core count is exact."""
+    code = ("import json, sys, time; sys.path.insert(0, %r); import oracle; oracle.build(); "
+            "t0 = time.perf_counter(); A, B, X, reps = oracle.solve(%d, %d); t = time.perf_counter() - t0; "
+            "print(json.dumps({'t': t, 'status': reps[0]['status'], 'eta': reps[0]['eta']}))" % (ROOT, n, seed))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    out = subprocess.run([sys.executable, "-c", code], env=env, check=True, capture_output=True, text=True)
+    r = json.loads(out.stdout.strip().splitlines()[-1])
+    assert r["status"] == 0 and r["eta"] < 16, r
+    t = r["t"]
     return {"value": (2.0 / 3.0) * n ** 3 / t / 1e12, "unit": "TFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle FP64 unpivoted LU + GMRES-IR solve at n=%d (same generator, seed %d), %.1f s "
-                      "single-threaded, rate by the same 2/3 n^3 formula" % (n, seed, t)}
+            "sample": "oracle FP64 unpivoted LU + GMRES-IR solve at n=%d (same generator, seed %d), %.1f s on one "
+                      "thread (OMP_NUM_THREADS=1), rate by the same 2/3 n^3 formula" % (n, seed, t)}
 
 
 def fp64_gpu_baseline(torch, mxp, n: int, seed: int) -> dict:
@@ -92,6 +180,10 @@ def fp64_gpu_baseline(torch, mxp, n: int, seed: int) -> dict:
 
 def main():
     args = parse()
+    if args.summarize_pmc:
+        return summarize_pmc(args)
+    if args.summarize_stats:
+        return summarize_stats(args)
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
               "(the multi-GPU design is described in DESIGN.md)" % args.gpus, file=sys.stderr)
@@ -120,6 +212,16 @@ def main():
         if timed_events:
             timed_events[1].record(stream)
         return fac, res
+
+    if args.traffic_run:
+        fac, res = step()
+        src = torch.empty(CALIB_BYTES, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)                          # the calibration copy: the run's last copy kernel
+        torch.cuda.synchronize()
+        print(json.dumps({"traffic_run": True, "info": fac.info, "status": res.status[0]}), flush=True)
+        return
 
     for _ in range(args.warmup):
         fac, res = step()
@@ -159,7 +261,15 @@ def main():
     else:
         roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
                 "frac": round(gbs / PEAK["hbm_gbs"], 4)}
-    roof.update({"traffic": None, "kernel": "k_gemm_update<%s,%s>" % (args.update, args.store),
+    traffic = None
+    tf = traffic_file(args)
+    if os.path.exists(tf):
+        rec = json.loads(open(tf).read().split("\n", 3)[3])
+        if rec["gemm_source_sha256_16"] == gemm_source_hash():   # counters taken on this kernel
+            traffic = round(rec["traffic_bytes_per_launch"])
+    roof.update({"traffic": traffic, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                 "algorithmic_bytes_per_launch": round(g["bytes"] / max(g["launches"], 1)),
+                 "kernel": "k_gemm_update<%s,%s>" % (args.update, args.store),
                  "launches": g["launches"], "avg_launch_us": round(1e3 * g["ms"] / max(g["launches"], 1), 2),
                  "mfma_tflops": round(tflops, 1), "mfma_frac": round(tflops / peak_fl, 4),
                  "intensity_flop_per_byte": round(intensity, 1), "ridge": round(ridge, 1),

@@ -445,37 +445,32 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
                   4.0 * m * (double)nb * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
         return hipGetLastError();
     };
-    // part: 0 = the whole trailing matrix, 1 = block column and block row k+1, 2 = the rest
-    auto update = [&](int64_t k, int part, hipStream_t st) -> hipError_t {
-        const int64_t m = n - k - nb;
+    // one trailing-update launch: C[0:M, 0:N] (offset c0 rows, c1 columns
+    // into A22) -= L21[c0:c0+M] U12[c1:c1+N]^T, each launch timed on its own
+    auto gemm = [&](int64_t k, int64_t c0, int64_t c1, int64_t M, int64_t N, hipStream_t st) -> hipError_t {
         const int set = (int)((k / nb) & 1);
         const OP_T* Lq = (const OP_T*)p.Lq + set * opset;
         const OP_T* Uq = (const OP_T*)p.Uq + set * opset;
         const float* sa = p.inv_sa + set * scset;
         const float* sb = p.inv_sb + set * scset;
-        ST_T* C = A + (k + nb) + (k + nb) * lda;
-        const int64_t c = nb;                       // width of block column / row k+1
+        ST_T* C = A + (k + nb + c0) + (k + nb + c1) * lda;
         hipEvent_t pt = prof::begin(st);
-        hipError_t e2 = hipSuccess;
-        double fl = 0, by = 0;
-        if (part == 0) {
-            e2 = gemm_update(OP, ST, C, lda, m, m, nb, Lq, Uq, sa, sb, st);
-            fl = 2.0 * m * (double)m * nb;
-            by = 2.0 * m * (double)m * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T);
-        } else if (part == 1) {
-            e2 = gemm_update(OP, ST, C, lda, m, c, nb, Lq, Uq, sa, sb, st);                 // block column
-            if (!e2)
-                e2 = gemm_update(OP, ST, C + c * lda, lda, c, m - c, nb, Lq, Uq + c * nb, sa, sb + c / 32, st);
-            fl = 2.0 * (2.0 * m - c) * c * nb;
-            by = 2.0 * (2.0 * m - c) * c * sizeof(ST_T) + (m + m) * (double)nb * sizeof(OP_T);
-        } else {
-            e2 = gemm_update(OP, ST, C + c + c * lda, lda, m - c, m - c, nb, Lq + c * nb, Uq + c * nb, sa + c / 32,
-                             sb + c / 32, st);
-            fl = 2.0 * (m - c) * (double)(m - c) * nb;
-            by = 2.0 * (m - c) * (double)(m - c) * sizeof(ST_T) + 2.0 * (m - c) * (double)nb * sizeof(OP_T);
-        }
-        prof::end(pt, prof::GEMM, st, fl, by);
+        hipError_t e2 = gemm_update(OP, ST, C, lda, M, N, nb, Lq + c0 * nb, Uq + c1 * nb, sa + c0 / 32, sb + c1 / 32,
+                                    st);
+        prof::end(pt, prof::GEMM, st, 2.0 * M * (double)N * nb,
+                  2.0 * M * (double)N * sizeof(ST_T) + (M + N) * (double)nb * sizeof(OP_T));
         return e2;
+    };
+    // part: 0 = the whole trailing matrix, 1 = block column and block row k+1, 2 = the rest
+    auto update = [&](int64_t k, int part, hipStream_t st) -> hipError_t {
+        const int64_t m = n - k - nb;
+        const int64_t c = nb;                       // width of block column / row k+1
+        if (part == 0) return gemm(k, 0, 0, m, m, st);
+        if (part == 1) {
+            hipError_t e2 = gemm(k, 0, 0, m, c, st);                    // block column
+            return e2 ? e2 : gemm(k, 0, c, c, m - c, st);              // block row
+        }
+        return gemm(k, c, c, m - c, m - c, st);
     };
 
     if ((e = fill_u64(p.info, 1, ~0ull, s))) return e;
