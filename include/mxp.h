@@ -60,7 +60,8 @@ enum {
     MXP_EHIP = -3,        /* a HIP runtime call failed; see mxp_last_error() */
     MXP_ESINGULAR = 1,    /* zero or non-finite pivot; *info = 1-based column */
     MXP_ENOCONV = 2,      /* refinement needed more than max_iters iterations */
-    MXP_ECRITERION = 3    /* refinement stopped but scaled residual >= tol */
+    MXP_ECRITERION = 3,   /* refinement stopped but scaled residual >= tol */
+    MXP_PENDING = 4       /* mxp_server_poll: the request is not done yet */
 };
 
 /* input scaling applied before the factorisation ("Algorithmic Framework":
@@ -218,6 +219,85 @@ int mxp_hpl_eta(int64_t n, uint64_t seed, const double *diag, const double *a_in
 int mxp_profile_enable(int on);
 int mxp_profile_reset(void);
 int mxp_profile_read(int cls, double *total_ms, double *flops, double *bytes, int64_t *launches);
+
+/*
+ * ---------------------------------------------------------------- serving
+ * A solve server on one device: requests (n, nrhs, seed) arrive at any
+ * time; each is generated, factored and refined exactly as by mxp_generate +
+ * mxp_factor + mxp_solve_ir.  Requests are admitted in arrival order as soon
+ * as a slot is free and their device memory fits in the HBM budget (the
+ * caller's arena, sub-allocated by the server); up to max_slots requests are
+ * in flight at once, each on its own stream, so that the kernels of requests
+ * at different stages overlap on the device (continuous batching).  The
+ * block size of each request is chosen by size class; with `autotune` the
+ * server times the candidate block sizes of every class on the device at
+ * creation and keeps the fastest.  The paper has no serving part; the calls
+ * follow its statement of the problem for every request.
+ *
+ * Ownership: `arena` is a device buffer of arena_bytes owned by the caller,
+ * valid until mxp_server_destroy returns.  x_host given to submit is a host
+ * buffer of n * nrhs doubles (column-major, ld n) that receives the solution
+ * (may be NULL); it must stay valid until the request is done.
+ * Thread safety: every call may be made from any thread.
+ */
+typedef struct mxp_server mxp_server;
+
+typedef struct {
+    int max_slots;      /* requests in flight at once (>= 1) */
+    int update;         /* update format, e.g. MXP_BF16 */
+    int store;          /* storage format of A and the factor, e.g. MXP_BF16 */
+    int nb;             /* block size; 0 = by size class (see autotune) */
+    int autotune;       /* nonzero: time the candidate block sizes at creation */
+    int restart;        /* GMRES restart length (1..64) */
+    int max_iters;      /* iteration cap of the refinement */
+    double tol;         /* HPL scaled-residual threshold, e.g. 16 */
+    double tau;         /* inner GMRES tolerance (mxp_solve_ir) */
+} mxp_server_cfg;
+
+typedef struct {
+    uint64_t id;
+    int64_t n, nrhs, nb;
+    int status;         /* MXP_OK or the first non-OK code of generate / factor / solve */
+    int pad;
+    int64_t iters;      /* largest iteration count over the right-hand sides */
+    double eta;         /* largest final scaled residual over the right-hand sides */
+    int64_t t_submit_ns, t_start_ns, t_done_ns;   /* steady clock, since server creation */
+} mxp_request_result;
+
+typedef struct {
+    int64_t submitted, completed, failed;
+    int64_t in_flight, peak_in_flight;
+    size_t arena_bytes, bytes_in_use, peak_bytes_in_use;
+} mxp_server_stats;
+
+/* device bytes one request needs (A, B, X, diag and all work spaces) */
+size_t mxp_server_request_bytes(int64_t n, int64_t nrhs, int64_t nb, int update, int store, int restart);
+
+/* creates the server (and, with cfg->autotune, runs the block-size tuner,
+ * which uses the arena and synchronises).  *out receives the handle. */
+int mxp_server_create(int device, void *arena, size_t arena_bytes, const mxp_server_cfg *cfg, mxp_server **out);
+
+/* queues a request; returns MXP_EINVAL if it can never fit the arena.
+ * *id receives its id (ids count from 1). */
+int mxp_server_submit(mxp_server *srv, int64_t n, int64_t nrhs, uint64_t seed, double *x_host, uint64_t *id);
+
+/* MXP_OK and *out filled if request `id` is done; MXP_PENDING if not yet;
+ * MXP_EINVAL for an unknown id */
+int mxp_server_poll(mxp_server *srv, uint64_t id, mxp_request_result *out);
+
+/* blocks until request `id` is done, then as mxp_server_poll */
+int mxp_server_wait(mxp_server *srv, uint64_t id, mxp_request_result *out);
+
+/* blocks until every submitted request is done */
+int mxp_server_drain(mxp_server *srv);
+
+int mxp_server_get_stats(mxp_server *srv, mxp_server_stats *out);
+
+/* block size the server uses for a request of size n */
+int64_t mxp_server_block_size(mxp_server *srv, int64_t n);
+
+/* drains, stops the slot threads and releases the server's streams */
+int mxp_server_destroy(mxp_server *srv);
 
 #ifdef __cplusplus
 }

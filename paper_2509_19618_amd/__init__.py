@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmxp.so")
 
 F64, F32, F16, BF16, F8E4M3 = 0, 1, 2, 3, 4
-OK, EINVAL, EWORKSPACE, EHIP, ESINGULAR, ENOCONV, ECRITERION = 0, -1, -2, -3, 1, 2, 3
+OK, EINVAL, EWORKSPACE, EHIP, ESINGULAR, ENOCONV, ECRITERION, PENDING = 0, -1, -2, -3, 1, 2, 3, 4
 SCALE_NONE, SCALE_ROW_EQUIL = 0, 1
 
 _DTYPE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f8": F8E4M3, "e4m3": F8E4M3, "fp8": F8E4M3}
@@ -39,6 +39,25 @@ class MxpError(RuntimeError):
 class _RhsReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("cycles", ctypes.c_int64), ("eta", ctypes.c_double),
                 ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class _ServerCfg(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int), ("update", ctypes.c_int), ("store", ctypes.c_int), ("nb", ctypes.c_int),
+                ("autotune", ctypes.c_int), ("restart", ctypes.c_int), ("max_iters", ctypes.c_int),
+                ("tol", ctypes.c_double), ("tau", ctypes.c_double)]
+
+
+class _RequestResult(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("n", ctypes.c_int64), ("nrhs", ctypes.c_int64), ("nb", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("pad", ctypes.c_int32), ("iters", ctypes.c_int64),
+                ("eta", ctypes.c_double), ("t_submit_ns", ctypes.c_int64), ("t_start_ns", ctypes.c_int64),
+                ("t_done_ns", ctypes.c_int64)]
+
+
+class _ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
+                ("in_flight", ctypes.c_int64), ("peak_in_flight", ctypes.c_int64), ("arena_bytes", ctypes.c_size_t),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t)]
 
 
 _lib = None
@@ -65,6 +84,15 @@ SIGNATURES = [
     ("mxp_profile_enable", _I, [_I]),
     ("mxp_profile_reset", _I, []),
     ("mxp_profile_read", _I, [_I, _P, _P, _P, _P]),
+    ("mxp_server_request_bytes", _SZ, [_I64, _I64, _I64, _I, _I, _I]),
+    ("mxp_server_create", _I, [_I, _P, _SZ, _P, _P]),
+    ("mxp_server_submit", _I, [_P, _I64, _I64, _U64, _P, _P]),
+    ("mxp_server_poll", _I, [_P, _U64, _P]),
+    ("mxp_server_wait", _I, [_P, _U64, _P]),
+    ("mxp_server_drain", _I, [_P]),
+    ("mxp_server_get_stats", _I, [_P, _P]),
+    ("mxp_server_block_size", _I64, [_P, _I64]),
+    ("mxp_server_destroy", _I, [_P]),
 ]
 
 PROF_GEMM, PROF_TRSM, PROF_DIAG, PROF_PREC, PROF_REGEN = 0, 1, 2, 3, 4
@@ -265,3 +293,104 @@ def profile_read(cls: int) -> dict:
     ms, fl, by, cnt = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
     _check(lib().mxp_profile_read(cls, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by), ctypes.byref(cnt)))
     return {"ms": ms.value, "flops": fl.value, "bytes": by.value, "launches": cnt.value}
+
+
+def server_request_bytes(n: int, nrhs: int, nb: int, update="bf16", store="bf16", restart: int = 30) -> int:
+    """Device bytes one served request needs (see include/mxp.h)."""
+    return int(lib().mxp_server_request_bytes(n, nrhs, nb, dtype_code(update), dtype_code(store), restart))
+
+
+@dataclass
+class RequestResult:
+    id: int
+    n: int
+    nrhs: int
+    nb: int
+    status: int
+    iters: int
+    eta: float
+    t_submit_ns: int
+    t_start_ns: int
+    t_done_ns: int
+
+    @property
+    def latency_ms(self) -> float:
+        return (self.t_done_ns - self.t_submit_ns) / 1e6
+
+
+class Server:
+    """Continuous-batching solve server on one device (mxp_server_* in
+    include/mxp.h).  The arena is a torch uint8 device tensor held by this
+    object; solutions land in host numpy arrays given at submission."""
+
+    def __init__(self, arena_bytes: int, max_slots: int = 4, update="bf16", store="bf16", nb: int = 0,
+                 autotune: bool = False, restart: int = 30, max_iters: int = 50, tol: float = 16.0,
+                 tau: float = 2.0 ** -50, device: int = 0):
+        self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device="cuda:%d" % device)
+        cfg = _ServerCfg(max_slots, dtype_code(update), dtype_code(store), nb, 1 if autotune else 0, restart,
+                         max_iters, tol, tau)
+        torch.cuda.synchronize(device)
+        h = ctypes.c_void_p()
+        _check(lib().mxp_server_create(device, _ptr(self.arena), self.arena.numel(), ctypes.byref(cfg),
+                                       ctypes.byref(h)))
+        self._h = h
+        self._x = {}
+
+    def submit(self, n: int, nrhs: int, seed: int, want_x: bool = True) -> int:
+        import numpy as np
+        x = np.empty((nrhs, n), dtype=np.float64) if want_x else None
+        rid = ctypes.c_uint64()
+        _check(lib().mxp_server_submit(self._h, n, nrhs, seed, x.ctypes.data if x is not None else None,
+                                       ctypes.byref(rid)))
+        self._x[rid.value] = x
+        return rid.value
+
+    @staticmethod
+    def _result(r: _RequestResult) -> RequestResult:
+        return RequestResult(r.id, r.n, r.nrhs, r.nb, r.status, r.iters, r.eta, r.t_submit_ns, r.t_start_ns,
+                             r.t_done_ns)
+
+    def poll(self, rid: int):
+        r = _RequestResult()
+        code = lib().mxp_server_poll(self._h, rid, ctypes.byref(r))
+        if code == PENDING:
+            return None
+        _check(code)
+        return self._result(r)
+
+    def wait(self, rid: int) -> RequestResult:
+        r = _RequestResult()
+        _check(lib().mxp_server_wait(self._h, rid, ctypes.byref(r)))
+        return self._result(r)
+
+    def solution(self, rid: int):
+        """The solution of a finished request, shape (nrhs, n) (row r = x_r)."""
+        return self._x[rid]
+
+    def drain(self) -> None:
+        _check(lib().mxp_server_drain(self._h))
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().mxp_server_get_stats(self._h, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _ServerStats._fields_}
+
+    def block_size(self, n: int) -> int:
+        return int(lib().mxp_server_block_size(self._h, n))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _check(lib().mxp_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmxp.so")
-SOURCES = ["api.hip", "gen.hip", "lu.hip", "diag.hip", "solve.hip", "prof.hip", "gemm.hip"]
+SOURCES = ["api.hip", "gen.hip", "lu.hip", "diag.hip", "solve.hip", "prof.hip", "gemm.hip", "server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -107,19 +107,19 @@ static hipError_t fill_f64(double* p, int64_t n, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
-extern "C" int mxp_factor(int64_t n, int64_t nb, int update, int store, int scaling, const double* diag, void* A,
-                          int64_t lda, void* aux, void* work, size_t work_bytes, int64_t* info, void* stream) {
+namespace mxp {
+int factor_with(int64_t n, int64_t nb, int update, int store, int scaling, const double* diag, void* A, int64_t lda,
+                void* aux, void* work, size_t work_bytes, int64_t* info, hipStream_t s, Lookahead* la) {
     if (n < 1 || n >= (1ll << 31) || !valid_pair(update, store) || !valid_nb(nb, update) || lda < n || !A || !aux ||
         !work || (scaling != MXP_SCALE_NONE && scaling != MXP_SCALE_ROW_EQUIL) ||
         (scaling == MXP_SCALE_ROW_EQUIL && !diag))
         return set_err(MXP_EINVAL, "mxp_factor: bad argument%s", "");
     if (work_bytes < work_layout(n, nb, update).total)
         return set_err(MXP_EWORKSPACE, "mxp_factor: work buffer too small%s", "");
-    hipStream_t s = (hipStream_t)stream;
     FactorPlan p = make_plan(n, nb, update, store, A, lda, aux, work);
     if (scaling == MXP_SCALE_ROW_EQUIL) HIPCHK(row_equilibrate(p, diag, s));
     else HIPCHK(fill_f64(p.rowscale, n, 1.0, s));
-    HIPCHK(factor_run(p, s));
+    HIPCHK(factor_run(p, s, la));
     if (info) {
         unsigned long long v = 0;
         HIPCHK(hipMemcpyAsync(&v, p.info, 8, hipMemcpyDeviceToHost, s));
@@ -128,6 +128,13 @@ extern "C" int mxp_factor(int64_t n, int64_t nb, int update, int store, int scal
         if (*info) return MXP_ESINGULAR;
     }
     return MXP_OK;
+}
+}  // namespace mxp
+
+extern "C" int mxp_factor(int64_t n, int64_t nb, int update, int store, int scaling, const double* diag, void* A,
+                          int64_t lda, void* aux, void* work, size_t work_bytes, int64_t* info, void* stream) {
+    return factor_with(n, nb, update, store, scaling, diag, A, lda, aux, work, work_bytes, info, (hipStream_t)stream,
+                       nullptr);
 }
 
 // ------------------------------------------------------------------ solve

@@ -392,13 +392,9 @@ size_t diag_lu_smem() { return (size_t)(2 * DW + 2) * TILE_F * sizeof(float); }
 template <int ST>
 static hipError_t diag_lu_typed(void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
                                 float* linv, float* uinv, unsigned long long* info, hipStream_t s) {
-    static bool attr_done = false;
-    if (!attr_done) {
-        hipError_t e = hipFuncSetAttribute((const void*)k_diag_lu<ST>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)diag_lu_smem());
-        if (e) return e;
-        attr_done = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_diag_lu<ST>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_lu_smem());
+    if (attr) return attr;
     k_diag_lu<ST><<<1, DT, diag_lu_smem(), s>>>((typename Store<ST>::T*)A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv,
                                                 info);
     return hipGetLastError();

@@ -327,14 +327,9 @@ static constexpr int gemm_lds_bytes() { return 4 * GSTG > GT * (GT * 2 + 16) ? 4
 template <int OP, int ST>
 static hipError_t gemm_typed(void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq, const void* Bq,
                              const float* inv_sa, const float* inv_sb, hipStream_t s) {
-    static bool attr_done = false;
-    hipError_t e;
-    if (!attr_done) {
-        if ((e = hipFuncSetAttribute((const void*)k_gemm_update<OP, ST>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     gemm_lds_bytes())))
-            return e;
-        attr_done = true;
-    }
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_gemm_update<OP, ST>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize, gemm_lds_bytes());
+    if (attr) return attr;
     const int tm = (int)((M + GT - 1) / GT), tn = (int)((N + GT - 1) / GT);
     const int nt = tm * tn;
     const int per_xcd = (nt + 7) / 8;

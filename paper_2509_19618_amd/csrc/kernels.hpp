@@ -60,7 +60,19 @@ hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, i
 hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
                    float* linv, float* uinv, unsigned long long* info, hipStream_t s);
 hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t s);
-hipError_t factor_run(const FactorPlan& p, hipStream_t s);
+// Side stream and events of the look-ahead (default stream priority).  A
+// factorisation uses the caller's context, or a per-device one if la is NULL;
+// concurrent factorisations need a context each.
+struct Lookahead {
+    hipStream_t side = nullptr;
+    hipEvent_t ev_cross = nullptr, ev_panel = nullptr;
+};
+hipError_t lookahead_create(Lookahead* la);
+void lookahead_destroy(Lookahead* la);
+hipError_t factor_run(const FactorPlan& p, hipStream_t s, Lookahead* la = nullptr);
+// mxp_factor with an explicit look-ahead context (api.hip)
+int factor_with(int64_t n, int64_t nb, int update, int store, int scaling, const double* diag, void* A, int64_t lda,
+                void* aux, void* work, size_t work_bytes, int64_t* info, hipStream_t s, Lookahead* la);
 
 // ---- preconditioner and GMRES pieces (solve.hip)
 struct PrecPlan {

@@ -13,6 +13,8 @@
 //      rounding to the update format under a power-of-two strip scale;
 //   3. A22 <- A22 - L21 U12 on the matrix cores (MFMA), FP32 accumulation,
 //      result rounded to the storage format.
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -357,25 +359,33 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
 
 // ============================================================== driver
 
-// Side stream and events for the look-ahead, one set per device (default
+hipError_t lookahead_create(Lookahead* la) {
+    hipError_t e;
+    if ((e = hipStreamCreateWithFlags(&la->side, hipStreamNonBlocking))) return e;
+    if ((e = hipEventCreateWithFlags(&la->ev_cross, hipEventDisableTiming))) return e;
+    return hipEventCreateWithFlags(&la->ev_panel, hipEventDisableTiming);
+}
+
+void lookahead_destroy(Lookahead* la) {
+    if (la->ev_panel) hipEventDestroy(la->ev_panel);
+    if (la->ev_cross) hipEventDestroy(la->ev_cross);
+    if (la->side) hipStreamDestroy(la->side);
+    *la = Lookahead();
+}
+
+// The look-ahead context of callers that bring none: one per device (default
 // stream priority; created on first use and kept for the process).
-struct Lookahead {
-    hipStream_t side = nullptr;
-    hipEvent_t ev_cross = nullptr, ev_panel = nullptr;
-};
 static Lookahead g_la[64];
+static std::mutex g_la_mutex;
 
 static hipError_t lookahead_for_device(Lookahead** out) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e) return e;
     if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_la_mutex);
     Lookahead& L = g_la[dev];
-    if (!L.side) {
-        if ((e = hipStreamCreateWithFlags(&L.side, hipStreamNonBlocking))) return e;
-        if ((e = hipEventCreateWithFlags(&L.ev_cross, hipEventDisableTiming))) return e;
-        if ((e = hipEventCreateWithFlags(&L.ev_panel, hipEventDisableTiming))) return e;
-    }
+    if (!L.side && (e = lookahead_create(&L))) return e;
     *out = &L;
     return hipSuccess;
 }
@@ -387,24 +397,24 @@ static hipError_t lookahead_for_device(Lookahead** out) {
 // stream performs the rest of the update.  Two operand sets alternate
 // between consecutive steps.
 template <int ST, int OP>
-static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
+static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la) {
     typedef typename Store<ST>::T ST_T;
     typedef typename Operand<OP>::T OP_T;
-    static bool attr_done = false;
+    static const hipError_t attr = []() {
+        hipError_t e2;
+        if ((e2 = hipFuncSetAttribute((const void*)k_trsm_L<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)trsm_smem(1024)))) return e2;
+        if ((e2 = hipFuncSetAttribute((const void*)k_trsm_U<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)trsm_smem(1024)))) return e2;
+        if ((e2 = hipFuncSetAttribute((const void*)k_inv_upper, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)trsm_smem(1024)))) return e2;
+        return hipFuncSetAttribute((const void*)k_inv_lower, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                   (int)trsm_smem(1024));
+    }();
+    if (attr) return attr;
     hipError_t e;
-    if (!attr_done) {
-        if ((e = hipFuncSetAttribute((const void*)k_trsm_L<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)trsm_smem(1024)))) return e;
-        if ((e = hipFuncSetAttribute((const void*)k_trsm_U<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)trsm_smem(1024)))) return e;
-        if ((e = hipFuncSetAttribute((const void*)k_inv_upper, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)trsm_smem(1024)))) return e;
-        if ((e = hipFuncSetAttribute((const void*)k_inv_lower, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                     (int)trsm_smem(1024)))) return e;
-        attr_done = true;
-    }
-    Lookahead* LA = nullptr;
-    if ((e = lookahead_for_device(&LA))) return e;
+    Lookahead* LA = la;
+    if (!LA && (e = lookahead_for_device(&LA))) return e;
     ST_T* A = (ST_T*)p.A;
     const int64_t n = p.n, lda = p.lda;
     const int nb = (int)p.nb;
@@ -508,15 +518,15 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s) {
     return hipSuccess;
 }
 
-hipError_t factor_run(const FactorPlan& p, hipStream_t s) {
+hipError_t factor_run(const FactorPlan& p, hipStream_t s, Lookahead* la) {
     const int u = p.update, t = p.store;
-    if (u == F32 && t == F32) return factor_typed<F32, F32>(p, s);
-    if (u == F16 && t == F16) return factor_typed<F16, F16>(p, s);
-    if (u == BF16 && t == BF16) return factor_typed<BF16, BF16>(p, s);
-    if (u == F8 && t == F16) return factor_typed<F16, F8>(p, s);
-    if (u == F8 && t == BF16) return factor_typed<BF16, F8>(p, s);
-    if (u == F16 && t == F32) return factor_typed<F32, F16>(p, s);
-    if (u == BF16 && t == F32) return factor_typed<F32, BF16>(p, s);
+    if (u == F32 && t == F32) return factor_typed<F32, F32>(p, s, la);
+    if (u == F16 && t == F16) return factor_typed<F16, F16>(p, s, la);
+    if (u == BF16 && t == BF16) return factor_typed<BF16, BF16>(p, s, la);
+    if (u == F8 && t == F16) return factor_typed<F16, F8>(p, s, la);
+    if (u == F8 && t == BF16) return factor_typed<BF16, F8>(p, s, la);
+    if (u == F16 && t == F32) return factor_typed<F32, F16>(p, s, la);
+    if (u == BF16 && t == F32) return factor_typed<F32, BF16>(p, s, la);
     return hipErrorInvalidValue;
 }
 

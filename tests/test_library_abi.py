@@ -67,3 +67,22 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(mxp, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         mxp.lib()
+
+
+def test_server_request_bytes_and_argument_checks():
+    L = mxp.lib()
+    b = [mxp.server_request_bytes(n, 1, 256) for n in (512, 1024, 4096, 16384)]
+    assert all(x > 0 for x in b) and b == sorted(b)
+    # at least A (16-bit, padded leading dimension) plus B, X and the factor's aux space
+    for n, x in zip((512, 1024, 4096, 16384), b):
+        assert x >= n * n * 2 + 2 * n * 8 + L.mxp_factor_aux_bytes(n, 256)
+    assert mxp.server_request_bytes(4096, 8, 256) > mxp.server_request_bytes(4096, 1, 256)
+    assert mxp.server_request_bytes(0, 1, 256) == 0
+    assert mxp.server_request_bytes(512, 0, 256) == 0
+    # invalid configurations are rejected before any device call
+    cfg = mxp._ServerCfg(0, mxp.BF16, mxp.BF16, 0, 0, 30, 50, 16.0, 2.0 ** -50)
+    h = ctypes.c_void_p()
+    assert L.mxp_server_create(0, ctypes.c_void_p(256), 1 << 20, ctypes.byref(cfg), ctypes.byref(h)) == mxp.EINVAL
+    cfg = mxp._ServerCfg(2, mxp.BF16, mxp.BF16, 96, 0, 30, 50, 16.0, 2.0 ** -50)
+    assert L.mxp_server_create(0, ctypes.c_void_p(256), 1 << 20, ctypes.byref(cfg), ctypes.byref(h)) == mxp.EINVAL
+    assert L.mxp_server_submit(None, 512, 1, 1, None, ctypes.byref(ctypes.c_uint64())) == mxp.EINVAL
