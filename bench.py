@@ -62,7 +62,69 @@ def parse():
     ap.add_argument("--summarize-stats", metavar="DIR",
                     help="turn a rocprofv3 --kernel-trace --stats csv output into a kernel-time summary")
     ap.add_argument("--cmd", default="", help="the rocprofv3 command(s) that produced the summarized output")
+    ap.add_argument("--serve", action="store_true",
+                    help="only the serving stream, full protocol (2000 requests at 0.5x and 0.8x saturation)")
+    ap.add_argument("--no-serving", action="store_true", help="leave the serving summary out of the default line")
+    ap.add_argument("--serve-slots", type=int, default=8)
     return ap.parse_args()
+
+
+def serving_stream(torch, mxp, n_requests: int, drop: int, loads, sat_requests: int, slots: int) -> dict:
+    """Serving stream: n log-uniform in [512, 16384], 1..8 right-hand sides,
+    request seed 1000 + id, BF16 update and storage, FP64 refinement.  The
+    saturated rate is measured first (all requests queued at once); then
+    Poisson arrivals (generator seed 7) at the given fractions of it.
+    Latency = completion - arrival; the first `drop` requests are warm-up."""
+    import numpy as np
+    rng = np.random.default_rng(7)
+
+    def draw(k):
+        n = np.floor(np.exp(rng.uniform(np.log(512), np.log(16384), k))).astype(np.int64)
+        r = rng.integers(1, 9, k)
+        return list(zip(n.tolist(), r.tolist()))
+
+    arena = int(1.25 * slots * mxp.server_request_bytes(16384, 8, 512))
+    srv = mxp.Server(arena, max_slots=slots, update="bf16", store="bf16", autotune=True)
+    try:
+        tuned = {n: srv.block_size(n) for n in (512, 1024, 2048, 4096, 8192, 16384)}
+        sat = draw(sat_requests)
+        t0 = time.perf_counter()
+        ids = [srv.submit(n, r, 1000 + k, want_x=False) for k, (n, r) in enumerate(sat)]
+        srv.drain()
+        t_sat = time.perf_counter() - t0
+        bad = sum(1 for i in ids if srv.wait(i).status != mxp.OK)
+        rate_sat = len(sat) / t_sat
+        out = {"saturated_solves_per_s": round(rate_sat, 2), "saturation_requests": len(sat),
+               "saturation_failed": bad, "slots": slots, "tuned_nb": tuned, "runs": []}
+        for frac in loads:
+            lam = frac * rate_sat
+            reqs = draw(n_requests)
+            gaps = rng.exponential(1.0 / lam, n_requests)
+            arrive = np.cumsum(gaps)
+            ids = []
+            t0 = time.perf_counter()
+            for k, (n, r) in enumerate(reqs):
+                dt = arrive[k] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                ids.append(srv.submit(n, r, 1000 + k, want_x=False))
+            srv.drain()
+            res = [srv.wait(i) for i in ids]
+            lat = np.array([x.latency_ms for x in res[drop:]])
+            ok = all(x.status == mxp.OK and x.eta < 16 for x in res)
+            span = (max(x.t_done_ns for x in res[drop:]) - min(x.t_submit_ns for x in res[drop:])) / 1e9
+            out["runs"].append({"load": frac, "lambda_per_s": round(lam, 2), "requests": n_requests, "dropped": drop,
+                                "solves_per_s": round((n_requests - drop) / span, 2),
+                                "p50_ms": round(float(np.percentile(lat, 50)), 3),
+                                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                                "mean_ms": round(float(lat.mean()), 3), "all_valid": ok,
+                                "max_iters": max(x.iters for x in res), "max_eta": max(x.eta for x in res),
+                                "peak_in_flight": srv.stats()["peak_in_flight"]})
+        return out
+    finally:
+        srv.close()
+        del srv
+        torch.cuda.empty_cache()
 
 
 def gemm_source_hash() -> str:
@@ -191,6 +253,17 @@ def main():
     import torch
     import paper_2509_19618_amd as mxp
 
+    if args.serve:
+        sv = serving_stream(torch, mxp, 2000, 200, (0.5, 0.8), 400, args.serve_slots)
+        r8 = sv["runs"][-1]
+        print(json.dumps({"metric": "served solves/s (serving stream, n log-uniform 512..16384, 1-8 RHS); p50/p99",
+                          "value": r8["solves_per_s"], "unit": "solves/s", "n_gpus": 1, "higher_is_better": True,
+                          "p50_ms": r8["p50_ms"], "p99_ms": r8["p99_ms"], "dtype": "bf16", "data": "synthetic",
+                          "config": {"workload": "serving stream, Poisson arrivals at 0.5x and 0.8x saturation, "
+                                                 "2000 requests, first 200 dropped"},
+                          "serving": sv}), flush=True)
+        return
+
     n, nb = args.n, args.nb
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
@@ -295,8 +368,15 @@ def main():
                                ("regen_matvec", mxp.PROF_REGEN))},
         "roofline": roof,
     }
-    del A0
+    del A0, aux, fwork, swork
+    prob = None
     torch.cuda.empty_cache()
+    if not args.no_serving:
+        sv = serving_stream(torch, mxp, 600, 60, (0.8,), 200, args.serve_slots)
+        r8 = sv["runs"][-1]
+        line["p50_ms_served"] = r8["p50_ms"]
+        line["p99_ms_served"] = r8["p99_ms"]
+        line["serving"] = sv
     if not args.no_fp64_baseline:
         fb = fp64_gpu_baseline(torch, mxp, n, args.seed)
         line["fp64_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in fb.items()}
