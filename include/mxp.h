@@ -180,7 +180,9 @@ int mxp_solve_ir(int64_t n, int64_t nb, int update, int store, uint64_t seed, co
  *   FP64, A regenerated from (seed, diag) -- the refinement's residual
  *   ("Algorithmic Framework": the 64-bit residual of the refinement).
  * mxp_apply_prec: Z = M^-1 V = U^-1 L^-1 S V for nrhs columns (nrhs <= 64),
- *   FP64 arithmetic on the stored factor (the left preconditioner).
+ *   FP64 arithmetic on the stored factor (the left preconditioner);
+ *   synchronises (it reads back an error word: MXP_EHIP if a wait of the
+ *   block-substitution kernels expired).  mxp_solve_ir reports the same.
  * mxp_hpl_eta: the HPL scaled residual of one right-hand side (x, b on the
  *   device) written to the host double *eta; synchronises.
  */

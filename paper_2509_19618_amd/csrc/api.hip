@@ -151,7 +151,7 @@ static SolveLayout solve_layout(int64_t n, int64_t nrhs, int restart) {
     L.r = off; off = al256(off + (size_t)n * 8);
     L.z = off; off = al256(off + (size_t)n * 8);
     L.P = off; off = al256(off + regen_partial_bytes(n, 8 < nrhs ? 8 : (int)std::max<int64_t>(nrhs, 1)));
-    L.W = off; off = al256(off + 2 * (size_t)n * std::max<int64_t>(nrhs, 1) * 8);
+    L.W = off; off = al256(off + prec_work_bytes(n, 1));
     L.part = off; off = al256(off + 2 * 256 * 8);
     L.epart = off; off = al256(off + 3 * 512 * 8);
     L.H = off; off = al256(off + (size_t)(m + 1) * m * 8);
@@ -206,6 +206,7 @@ extern "C" int mxp_solve_ir(int64_t n, int64_t nb, int update, int store, uint64
     double* sc = (double*)(wb + L.sc);  // [0..2] eta out, [4] beta, [5] xnorm, [6..7] flag
     const int m = restart, ldh = restart + 1;
     PrecPlan pp = make_prec(n, nb, store, LU, lda, aux);
+    HIPCHK(prec_err_reset(W, n, 1, s));
     int worst = MXP_OK;
     for (int64_t rr = 0; rr < nrhs; ++rr) {
         const double* b = B + rr * ldb;
@@ -257,6 +258,9 @@ extern "C" int mxp_solve_ir(int64_t n, int64_t nb, int update, int store, uint64
         rep[rr].pad = 0;
         if (status > worst) worst = status;
     }
+    int perr = 0;
+    HIPCHK(prec_err_read(W, n, 1, &perr, s));
+    if (perr) return set_err(MXP_EHIP, "mxp_solve_ir: a wait of the block substitution expired%s", "");
     return worst;
 }
 
@@ -278,8 +282,8 @@ extern "C" int mxp_residual(int64_t n, uint64_t seed, const double* diag, const 
 }
 
 extern "C" size_t mxp_apply_prec_work_bytes(int64_t n, int64_t nrhs) {
-    if (n < 1 || nrhs < 1) return 0;
-    return 2 * (size_t)n * nrhs * 8;
+    if (n < 1 || nrhs < 1 || nrhs > 64) return 0;
+    return prec_work_bytes(n, (int)nrhs);
 }
 
 extern "C" int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, const void* LU, int64_t lda,
@@ -291,7 +295,12 @@ extern "C" int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, cons
     if (work_bytes < mxp_apply_prec_work_bytes(n, nrhs))
         return set_err(MXP_EWORKSPACE, "mxp_apply_prec: work buffer too small%s", "");
     PrecPlan pp = make_prec(n, nb, store, LU, lda, aux);
-    HIPCHK(prec_apply(pp, V, ldv, Z, ldz, (int)nrhs, (double*)work, (hipStream_t)stream));
+    hipStream_t s = (hipStream_t)stream;
+    HIPCHK(prec_err_reset((double*)work, n, (int)nrhs, s));
+    HIPCHK(prec_apply(pp, V, ldv, Z, ldz, (int)nrhs, (double*)work, s));
+    int perr = 0;
+    HIPCHK(prec_err_read((double*)work, n, (int)nrhs, &perr, s));
+    if (perr) return set_err(MXP_EHIP, "mxp_apply_prec: a wait of the block substitution expired%s", "");
     return MXP_OK;
 }
 

@@ -87,9 +87,14 @@ struct PrecPlan {
     const float* linv_full;
     const float* uinv_full;
 };
-// Z = U^-1 L^-1 S V for nr columns (V may alias Z); W: 2 x n x nr scratch (FP64)
+// Z = U^-1 L^-1 S V for nr columns (V may alias Z); W: prec_work_bytes(n, nr)
+// of scratch.  A wait of the substitution kernels that expires sets an error
+// word in W (cleared by prec_err_reset, read by prec_err_read).
+size_t prec_work_bytes(int64_t n, int nr);
 hipError_t prec_apply(const PrecPlan& p, const double* V, int64_t ldv, double* Z, int64_t ldz, int nr, double* W,
                       hipStream_t s);
+hipError_t prec_err_reset(double* W, int64_t n, int nr, hipStream_t s);
+hipError_t prec_err_read(double* W, int64_t n, int nr, int* err, hipStream_t s);
 
 hipError_t mgs_step(int64_t n, const double* V, int k, double* w, double* hcol, double* part, hipStream_t s);
 hipError_t norm_normalize(int64_t n, double* w, double* vout, double* hsub, double* part, hipStream_t s);

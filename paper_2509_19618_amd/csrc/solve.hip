@@ -3,10 +3,10 @@
 // preconditioner, GMRES in 64-bit, at most 50 iterations).
 //
 // prec_apply: z = U^-1 L^-1 S v by block forward and backward substitution
-// on the stored factor (FP64 arithmetic): the nb x nb diagonal blocks use the
-// FP32 L11\U11 kept by the factorisation with the inverses of their 64x64
-// diagonal sub-blocks; the off-diagonal panels are read in the storage
-// format (L21 strips unscaled by their power-of-two factor).
+// on the stored factor (FP64 arithmetic): the nb x nb diagonal blocks are
+// applied through the full FP32 inverses kept by the factorisation, the
+// off-diagonal panels are read in the storage format (L21 strips unscaled by
+// their power-of-two factor); one dataflow kernel per triangular solve.
 // Modified Gram-Schmidt, Givens rotations, the least-squares solve and the
 // basis update are deterministic (fixed reduction orders).
 #include "common.hpp"
@@ -25,79 +25,190 @@ __global__ __launch_bounds__(256) void k_scale_rows(int64_t n, const double* __r
     for (int r = 0; r < nr; ++r) W[i + r * n] = S[i] * V[i + r * ldv];
 }
 
-__global__ __launch_bounds__(256) void k_copy_cols(int64_t n, const double* __restrict__ W, double* __restrict__ Z,
-                                                   int64_t ldz, int nr) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    for (int r = 0; r < nr; ++r) Z[i + r * ldz] = W[i + r * n];
-}
+// ---------------------------------------------------------------- block substitution
+// One kernel per triangular solve.  Work-group = one strip of TS rows; strips
+// are processed as a dataflow: a strip of block j accumulates the products of
+// its rows of the off-diagonal factor with every dependency block's solution
+// as soon as that block is published (flag `ready`), then the strips of block
+// j meet (flag `cnt`) and each applies its rows of the FP32 inverse of the
+// diagonal block and publishes them.  Forward (L): dependencies are the blocks
+// before j, strips run in increasing order; backward (U): the blocks after j,
+// strips in decreasing order.  Work-groups are dispatched in index order and
+// every wait is on a strip of smaller index (or of the same block), so the
+// chain always progresses; each wait is still bounded and on expiry sets
+// *err and lets the work-group exit.  All sums are taken in a fixed order
+// (deterministic results).
+constexpr int TS = 64;
 
-// Diagonal-block solve with the full FP32 inverse: Y[k:k+kb] = Inv_k R[k:k+kb]
-// (FP64 arithmetic).  Work-group = 64 rows; its 4 waves split the columns and
-// their partial sums are added in a fixed order.  blockIdx.y = right-hand side.
-__global__ __launch_bounds__(256) void k_prec_diag(int64_t n, int64_t k, int kb, int nb, const float* __restrict__ inv,
-                                                   const double* __restrict__ R, double* __restrict__ Y) {
-    __shared__ double part[4][64];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const int row = blockIdx.x * 64 + lane;
-    const double* rhs = R + (int64_t)blockIdx.y * n + k;
-    const int q = (kb + 3) / 4;
-    const int c0 = wv * q, c1 = (c0 + q < kb) ? c0 + q : kb;
-    double acc = 0.0;
-    if (row < kb) {
-        const float* col = inv + row;
-#pragma unroll 8
-        for (int c = c0; c < c1; ++c) acc += (double)col[(int64_t)c * nb] * rhs[c];
+// Values exchanged between work-groups (block solutions, block right-hand
+// sides) are written and read with device-scope atomic accesses, which go to
+// the device's coherence point instead of an XCD's L2; a flag is raised only
+// after every wave has its stores acknowledged, so no cache write-back or
+// invalidation is needed.
+MXP_DEV void put_shared(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MXP_DEV double get_shared(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+__device__ bool wait_flag(const unsigned* flag, unsigned target, int* err, int* s_abort) {
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned it = 0;
+        while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            // a wait that expired anywhere ends every other wait at once
+            if (++it > (1u << 24) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                atomicOr(err, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        *s_abort = !ok;
     }
-    part[wv][lane] = acc;
     __syncthreads();
-    if (wv == 0 && row < kb) Y[(int64_t)blockIdx.y * n + k + row] = (part[0][lane] + part[1][lane]) +
-                                                                    (part[2][lane] + part[3][lane]);
+    return !*s_abort;
 }
 
-// Panel update R[rows] -= P z with z = Y[k:k+kb]: lower, rows k+kb..n-1 of
-// L21 (each stored 32-row strip divided by its scale); upper, rows 0..k-1 of
-// the U12 blocks above the diagonal block.  Thread = 2 consecutive rows; the
-// 4 waves split the kb columns; partials added in a fixed order.
+// every wave waits for its stores to be acknowledged, then the flag counts
+// one more strip
+__device__ void signal_flag(unsigned* flag) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int ST, bool LOWER>
-__global__ __launch_bounds__(256) void k_prec_panel(int64_t n, int64_t k, int kb, const typename Store<ST>::T* A,
-                                                    int64_t lda, const float* __restrict__ lsc_blk,
-                                                    const double* __restrict__ Y, double* __restrict__ R) {
-    __shared__ double z[1024];
-    __shared__ double part[4][128];
+__global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename Store<ST>::T* __restrict__ A,
+                                              int64_t lda, int vec, const float* __restrict__ inv_all,
+                                              const float* __restrict__ lsc, int64_t nstrips32,
+                                              const double* __restrict__ rhs, double* __restrict__ tbuf,
+                                              double* __restrict__ out, unsigned* flags, int* err) {
+    typedef typename Store<ST>::T T;
+    constexpr int RPL = 16 / (int)sizeof(T);   // rows per lane: one 16-byte load
+    constexpr int RG = TS / RPL;               // lanes per column
+    constexpr int CPI = 64 / RG;               // columns per wave and load
+    static_assert(CPI >= 4, "part[][] also holds the four column groups of the diagonal apply");
+    __shared__ double zs[1024];
+    __shared__ double part[4][CPI][TS];
+    __shared__ double w[TS];
+    __shared__ int s_abort;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    const double* y = Y + (int64_t)blockIdx.y * n + k;
-    double* rhs = R + (int64_t)blockIdx.y * n;
-    for (int i = tid; i < kb; i += 256) z[i] = y[i];
-    __syncthreads();
-    const int64_t rbeg = LOWER ? k + kb : 0, rend = LOWER ? n : k;
-    const int64_t row = rbeg + (int64_t)blockIdx.x * 128 + 2 * lane;
-    const int q = (kb + 3) / 4;
-    const int c0 = wv * q, c1 = (c0 + q < kb) ? c0 + q : kb;
-    double a0 = 0.0, a1 = 0.0;
-    if (row + 1 < rend) {
-        const typename Store<ST>::T* p = A + row + k * lda;
-#pragma unroll 8
-        for (int c = c0; c < c1; ++c) {
-            const int64_t o = (int64_t)c * lda;
-            a0 += (double)Store<ST>::load(p, o) * z[c];
-            a1 += (double)Store<ST>::load(p, o + 1) * z[c];
+    const int64_t S = (n + TS - 1) / TS, J = (n + nb - 1) / nb;
+    const int64_t sidx = LOWER ? (int64_t)blockIdx.x : S - 1 - (int64_t)blockIdx.x;
+    const int64_t j = sidx / (nb / TS);
+    const int64_t r0 = sidx * TS;
+    const int rows = (int)(n - r0 < TS ? n - r0 : TS);
+    unsigned* cnt = flags;
+    unsigned* ready = flags + J;
+    auto strips_of = [&](int64_t b) -> unsigned {
+        const int64_t kb = n - b * nb < nb ? n - b * nb : nb;
+        return (unsigned)((kb + TS - 1) / TS);
+    };
+    if (tid < TS) w[tid] = (tid < rows) ? rhs[r0 + tid] : 0.0;
+    const bool vload = vec && rows == TS;
+    const int rg = lane % RG, cl = lane / RG;
+    for (int64_t i = LOWER ? 0 : J - 1; i != j; i += LOWER ? 1 : -1) {
+        if (!wait_flag(&ready[i], strips_of(i), err, &s_abort)) return;
+        const int64_t c0 = i * nb;
+        const int kbi = (int)(n - c0 < nb ? n - c0 : nb);
+        for (int c = tid; c < kbi; c += 256) zs[c] = get_shared(out + c0 + c);
+        __syncthreads();
+        double acc[RPL];
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) acc[k] = 0.0;
+        const int q = (kbi + 3) / 4, cb = wv * q, ce = (cb + q < kbi) ? cb + q : kbi;
+        const T* base = A + r0 + RPL * rg + c0 * lda;
+        if (vload) {
+#pragma unroll 4
+            for (int c = cb + cl; c < ce; c += CPI) {
+                const uint4 v = *(const uint4*)(base + (int64_t)c * lda);
+                const T* e = (const T*)&v;
+                const double zc = zs[c];
+#pragma unroll
+                for (int k = 0; k < RPL; ++k) acc[k] += (double)Store<ST>::load(e, k) * zc;
+            }
+        } else {
+            for (int c = cb + cl; c < ce; c += CPI) {
+                const double zc = zs[c];
+#pragma unroll
+                for (int k = 0; k < RPL; ++k)
+                    if (RPL * rg + k < rows) acc[k] += (double)Store<ST>::load(base, (int64_t)c * lda + k) * zc;
+            }
         }
-    } else if (row < rend) {
-        const typename Store<ST>::T* p = A + row + k * lda;
-        for (int c = c0; c < c1; ++c) a0 += (double)Store<ST>::load(p, (int64_t)c * lda) * z[c];
-    }
-    part[wv][2 * lane] = a0;
-    part[wv][2 * lane + 1] = a1;
-    __syncthreads();
-    if (tid < 128) {
-        const int64_t r = rbeg + (int64_t)blockIdx.x * 128 + tid;
-        if (r < rend) {
-            double t = (part[0][tid] + part[1][tid]) + (part[2][tid] + part[3][tid]);
-            if (LOWER) t /= (double)lsc_blk[r / 32];
-            rhs[r] -= t;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) part[wv][cl][RPL * rg + k] = acc[k];
+        __syncthreads();
+        if (tid < rows) {
+            double t = 0.0;
+            for (int u = 0; u < 4; ++u)
+                for (int v2 = 0; v2 < CPI; ++v2) t += part[u][v2][tid];
+            if (LOWER) t /= (double)lsc[i * nstrips32 + (r0 + tid) / 32];
+            w[tid] -= t;
         }
     }
+    // this strip's rows of the block right-hand side are final
+    if (tid < rows) put_shared(tbuf + r0 + tid, w[tid]);
+    signal_flag(&cnt[j]);
+    if (!wait_flag(&cnt[j], strips_of(j), err, &s_abort)) return;
+    const int64_t cj = j * nb;
+    const int kbj = (int)(n - cj < nb ? n - cj : nb);
+    for (int c = tid; c < kbj; c += 256) zs[c] = get_shared(tbuf + cj + c);
+    __syncthreads();
+    // this strip's rows of the diagonal-block inverse (lower / upper
+    // triangular: only the columns up to / from the strip's rows), four rows
+    // per lane with 16-byte loads, the waves splitting the columns
+    {
+        const int rl0 = (int)(r0 - cj);
+        const int clo = LOWER ? 0 : rl0, chi = LOWER ? (rl0 + TS < kbj ? rl0 + TS : kbj) : kbj;
+        const int q = (chi - clo + 3) / 4, cb = clo + wv * q, ce = (cb + q < chi) ? cb + q : chi;
+        const int rsub = lane % 16, csub = lane / 16;
+        const float* colbase = inv_all + j * (int64_t)nb * nb + rl0 + 4 * rsub;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+        for (int c = cb + csub; c < ce; c += 4) {
+            const float4 v = *(const float4*)(colbase + (int64_t)c * nb);
+            const double zc = zs[c];
+            acc[0] += (double)v.x * zc;
+            acc[1] += (double)v.y * zc;
+            acc[2] += (double)v.z * zc;
+            acc[3] += (double)v.w * zc;
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) part[wv][csub][4 * rsub + k] = acc[k];
+    }
+    __syncthreads();
+    if (tid < rows) {
+        double t = 0.0;
+        for (int u = 0; u < 4; ++u)
+            for (int v2 = 0; v2 < 4; ++v2) t += part[u][v2][tid];
+        put_shared(out + r0 + tid, t);
+    }
+    signal_flag(&ready[j]);
+}
+
+__global__ void k_zero_u32(unsigned* p, int64_t count) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < count) p[i] = 0u;
+}
+
+static int64_t trsv_flag_words(int64_t n) { return 4 * (n / TS + 2) + 2; }
+
+size_t prec_work_bytes(int64_t n, int nr) {
+    // R (n x nr), Y, Tb (n each), flags + error word
+    return (size_t)(n * nr + 2 * n) * 8 + (size_t)trsv_flag_words(n) * 4 + 256;
+}
+
+static int* prec_err_word(double* W, int64_t n, int nr) {
+    return (int*)((unsigned*)(W + n * nr + 2 * n) + trsv_flag_words(n) - 2);
+}
+
+hipError_t prec_err_reset(double* W, int64_t n, int nr, hipStream_t s) {
+    k_zero_u32<<<1, 256, 0, s>>>((unsigned*)prec_err_word(W, n, nr), 1);
+    return hipGetLastError();
+}
+
+hipError_t prec_err_read(double* W, int64_t n, int nr, int* err, hipStream_t s) {
+    hipError_t e = hipMemcpyAsync(err, prec_err_word(W, n, nr), sizeof(int), hipMemcpyDeviceToHost, s);
+    if (!e) e = hipStreamSynchronize(s);
+    return e;
 }
 
 template <int ST>
@@ -105,33 +216,24 @@ static hipError_t prec_typed(const PrecPlan& p, const double* V, int64_t ldv, do
                              double* W, hipStream_t s) {
     typedef typename Store<ST>::T T;
     const int64_t n = p.n, nb = p.nb;
-    const int64_t nblk = (n + nb - 1) / nb;
-    const int64_t nstrips_total = (n + 31) / 32;
-    double* R = W;                 // right-hand side, updated by the panels
-    double* Y = W + n * nr;        // forward result, then the backward right-hand side
-    unsigned rows_g = (unsigned)((n + 255) / 256);
+    const int64_t J = (n + nb - 1) / nb;
+    const int64_t nstrips32 = (n + 31) / 32;
+    const int64_t S = (n + TS - 1) / TS;
+    double* R = W;                 // S V, nr columns
+    double* Y = W + n * nr;        // forward solution
+    double* Tb = Y + n;            // block right-hand sides
+    unsigned* flags = (unsigned*)(Tb + n);
+    int* err = prec_err_word(W, n, nr);
+    const int vec = ((p.lda * (int64_t)sizeof(T)) % 16 == 0 && ((uintptr_t)p.A) % 16 == 0) ? 1 : 0;
     hipEvent_t pt = prof::begin(s);
-    k_scale_rows<<<rows_g, 256, 0, s>>>(n, p.rowscale, V, ldv, R, nr);
-    for (int64_t b = 0; b < nblk; ++b) {         // L y = S v
-        int64_t k = b * nb;
-        int kb = (int)(n - k < nb ? n - k : nb);
-        k_prec_diag<<<dim3((unsigned)((kb + 63) / 64), nr), 256, 0, s>>>(n, k, kb, (int)nb, p.linv_full + b * nb * nb,
-                                                                        R, Y);
-        int64_t m = n - k - kb;
-        if (m > 0)
-            k_prec_panel<ST, true><<<dim3((unsigned)((m + 127) / 128), nr), 256, 0, s>>>(
-                n, k, kb, (const T*)p.A, p.lda, p.lsc + b * nstrips_total, Y, R);
+    k_scale_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, p.rowscale, V, ldv, R, nr);
+    for (int r = 0; r < nr; ++r) {
+        k_zero_u32<<<(unsigned)((4 * J + 255) / 256), 256, 0, s>>>(flags, 4 * J);
+        k_trsv<ST, true><<<(unsigned)S, 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, vec, p.linv_full, p.lsc,
+                                                     nstrips32, R + r * n, Tb, Y, flags, err);
+        k_trsv<ST, false><<<(unsigned)S, 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, vec, p.uinv_full, nullptr,
+                                                      nstrips32, Y, Tb, Z + r * ldz, flags + 2 * J, err);
     }
-    for (int64_t b = nblk - 1; b >= 0; --b) {    // U z = y
-        int64_t k = b * nb;
-        int kb = (int)(n - k < nb ? n - k : nb);
-        k_prec_diag<<<dim3((unsigned)((kb + 63) / 64), nr), 256, 0, s>>>(n, k, kb, (int)nb, p.uinv_full + b * nb * nb,
-                                                                        Y, R);
-        if (k > 0)
-            k_prec_panel<ST, false><<<dim3((unsigned)((k + 127) / 128), nr), 256, 0, s>>>(n, k, kb, (const T*)p.A,
-                                                                                        p.lda, nullptr, R, Y);
-    }
-    k_copy_cols<<<rows_g, 256, 0, s>>>(n, R, Z, ldz, nr);
     prof::end(pt, prof::PREC, s, 2.0 * n * (double)n * nr, (double)n * n * sizeof(T) + 8.0 * n * nb);
     return hipGetLastError();
 }
