@@ -135,22 +135,45 @@ __global__ __launch_bounds__(DT) void k_diag_lu(typename Store<ST>::T* A, int64_
         return __builtin_amdgcn_readfirstlane(v);
     };
 
-    // ---- load: T <- A11 in FP32, padded with the identity (branch-free, so
-    // that the loads of a tile are all in flight together)
+    // ---- load: T <- A11 in FP32, padded with the identity
     if (tid == 0) s_cnt[0] = s_cnt[1] = 0;
-    for (int u = wave; u < P * P; u += DW) {
-        const int I = u % P, J = u / P;
-        const int i = 32 * I + lr;
-        float v[16];
+    typedef typename Store<ST>::T ET;
+    constexpr int RPL = 16 / (int)sizeof(ET);                // rows per 16-byte load
+    const ET* A0 = A + k + k * lda;
+    if (kb == kbp && (lda * (int64_t)sizeof(ET)) % 16 == 0 && ((uintptr_t)A0) % 16 == 0) {
+        // whole columns, 16-byte loads (RPL rows per lane), four columns in flight per wave
+        for (int r0 = RPL * lane; r0 < kbp; r0 += 64 * RPL) {
+            for (int j0 = 4 * wave; j0 < kbp; j0 += 4 * DW) {
+                uint4 raw[4];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int j = 32 * J + 2 * q + lh;
-            const bool in = i < kb && j < kb;
-            v[q] = Store<ST>::load(A, in ? (k + i) + (k + j) * lda : k + k * lda);
-            v[q] = in ? v[q] : ((i == j) ? 1.0f : 0.0f);
+                for (int c = 0; c < 4; ++c) raw[c] = *(const uint4*)(A0 + r0 + (int64_t)(j0 + c) * lda);
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const ET* e = (const ET*)&raw[c];
+                    float* dst = T + r0 + (int64_t)(j0 + c) * ldt;
+#pragma unroll
+                    for (int m = 0; m < RPL; m += 4)
+                        *(float4*)(dst + m) = make_float4(Store<ST>::load(e, m), Store<ST>::load(e, m + 1),
+                                                          Store<ST>::load(e, m + 2), Store<ST>::load(e, m + 3));
+                }
+            }
         }
+    } else {
+        // ragged block: tile by tile, branch-free so that a tile's loads are in flight together
+        for (int u = wave; u < P * P; u += DW) {
+            const int I = u % P, J = u / P;
+            const int i = 32 * I + lr;
+            float v[16];
 #pragma unroll
-        for (int q = 0; q < 16; ++q) T[i + (int64_t)(32 * J + 2 * q + lh) * ldt] = v[q];
+            for (int q = 0; q < 16; ++q) {
+                const int j = 32 * J + 2 * q + lh;
+                const bool in = i < kb && j < kb;
+                v[q] = Store<ST>::load(A, in ? (k + i) + (k + j) * lda : k + k * lda);
+                v[q] = in ? v[q] : ((i == j) ? 1.0f : 0.0f);
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) T[i + (int64_t)(32 * J + 2 * q + lh) * ldt] = v[q];
+        }
     }
     __syncthreads();
 
@@ -182,7 +205,7 @@ __global__ __launch_bounds__(DT) void k_diag_lu(typename Store<ST>::T* A, int64_
             // step j; columns left of C0 are left alone (junk for j >= C0)
             auto lu_step = [&](int j, auto C0) {
                 const float xj = x[j];
-                const float rp = 1.0f / rl(xj, j);
+                const float rp = __builtin_amdgcn_rcpf(rl(xj, j));   // v_rcp_f32 (1 ulp)
                 dinv = (lr == j) ? rp : dinv;
                 if (lr > j) {
                     // rows at or above the pivot stay as they are (readlane
@@ -194,10 +217,14 @@ __global__ __launch_bounds__(DT) void k_diag_lu(typename Store<ST>::T* A, int64_
                 }
             };
 #pragma unroll 1
-            for (int j = 0; j < 16; ++j) lu_step(j, std::integral_constant<int, 0>());
+            for (int j = 0; j < 8; ++j) lu_step(j, std::integral_constant<int, 0>());
 #pragma unroll 1
-            for (int j = 16; j < 31; ++j) lu_step(j, std::integral_constant<int, 16>());
-            dinv = (lr == 31) ? 1.0f / rl(x[31], 31) : dinv;
+            for (int j = 8; j < 16; ++j) lu_step(j, std::integral_constant<int, 8>());
+#pragma unroll 1
+            for (int j = 16; j < 24; ++j) lu_step(j, std::integral_constant<int, 16>());
+#pragma unroll 1
+            for (int j = 24; j < 31; ++j) lu_step(j, std::integral_constant<int, 24>());
+            dinv = (lr == 31) ? __builtin_amdgcn_rcpf(rl(x[31], 31)) : dinv;
             const int o = 32 * (t & 1);
             float* L64 = linv + (t >> 1) * 4096;   // column-major 64 x 64
             float* U64 = uinv + (t >> 1) * 4096;   // row-major 64 x 64
@@ -227,16 +254,27 @@ __global__ __launch_bounds__(DT) void k_diag_lu(typename Store<ST>::T* A, int64_
                 // L^-1 by rows: X[i] = e_i - sum_{s<i} L[i][s] X[s]
                 // (row s of X is zero right of s: the sweep stops at C1)
                 auto linv_step = [&](int s2, auto C1) {
+                    constexpr int c1 = decltype(C1)::value;
                     if (lr > s2) {
                         const float l = sA[s2 * TP + lr];
+                        // all broadcasts first (kept apart from the FMAs so that
+                        // the readlane results pipeline instead of alternating)
+                        float pv[c1];
 #pragma unroll
-                        for (int c = 0; c < decltype(C1)::value; ++c) X[c] = fmaf(-l, rl(X[c], s2), X[c]);
+                        for (int c = 0; c < c1; ++c) pv[c] = rl(X[c], s2);
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int c = 0; c < c1; ++c) X[c] = fmaf(-l, pv[c], X[c]);
                     }
                 };
 #pragma unroll 1
-                for (int s2 = 0; s2 < 16; ++s2) linv_step(s2, std::integral_constant<int, 16>());
+                for (int s2 = 0; s2 < 8; ++s2) linv_step(s2, std::integral_constant<int, 8>());
 #pragma unroll 1
-                for (int s2 = 16; s2 < 31; ++s2) linv_step(s2, std::integral_constant<int, 32>());
+                for (int s2 = 8; s2 < 16; ++s2) linv_step(s2, std::integral_constant<int, 16>());
+#pragma unroll 1
+                for (int s2 = 16; s2 < 24; ++s2) linv_step(s2, std::integral_constant<int, 24>());
+#pragma unroll 1
+                for (int s2 = 24; s2 < 31; ++s2) linv_step(s2, std::integral_constant<int, 32>());
                 if (lh == 0) {
 #pragma unroll
                     for (int c = 0; c < 32; ++c) {
@@ -254,14 +292,22 @@ __global__ __launch_bounds__(DT) void k_diag_lu(typename Store<ST>::T* A, int64_
                     for (int c = decltype(C0)::value; c < 32; ++c) X[c] *= sc;
                     const float w = x[s2];
                     if (lr < s2) {
+                        float pv[32];
 #pragma unroll
-                        for (int c = decltype(C0)::value; c < 32; ++c) X[c] = fmaf(-w, rl(X[c], s2), X[c]);
+                        for (int c = decltype(C0)::value; c < 32; ++c) pv[c] = rl(X[c], s2);
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int c = decltype(C0)::value; c < 32; ++c) X[c] = fmaf(-w, pv[c], X[c]);
                     }
                 };
 #pragma unroll 1
-                for (int s2 = 31; s2 >= 16; --s2) uinv_step(s2, std::integral_constant<int, 16>());
+                for (int s2 = 31; s2 >= 24; --s2) uinv_step(s2, std::integral_constant<int, 24>());
 #pragma unroll 1
-                for (int s2 = 15; s2 >= 0; --s2) uinv_step(s2, std::integral_constant<int, 0>());
+                for (int s2 = 23; s2 >= 16; --s2) uinv_step(s2, std::integral_constant<int, 16>());
+#pragma unroll 1
+                for (int s2 = 15; s2 >= 8; --s2) uinv_step(s2, std::integral_constant<int, 8>());
+#pragma unroll 1
+                for (int s2 = 7; s2 >= 0; --s2) uinv_step(s2, std::integral_constant<int, 0>());
                 if (lh == 0) {
 #pragma unroll
                     for (int c = 0; c < 32; ++c) sUinv[c * TP + lr] = X[c];
