@@ -70,6 +70,7 @@ def lib():
             "orc_lu_solve": (None, [i64, P, i64, P]),
             "orc_hpl_eta": (dbl, [i64, P, i64, P, P]),
             "orc_residual_regen": (None, [i64, u64, P, P, P]),
+            "orc_residual_rows": (None, [i64, u64, P, P, P, i64, P]),
             "orc_hpl_eta_regen": (dbl, [i64, u64, P, P]),
             "orc_jacobi_regen": (i64, [i64, u64, P, P, i64, dbl]),
             "orc_gmres_cycle": (i64, [i64, P, i64, P, i64, P, P, i64, dbl, P, i64, P, P, P, P]),
@@ -161,6 +162,15 @@ def residual_regen(n: int, seed: int, x, b) -> np.ndarray:
     r = np.zeros(n)
     lib().orc_residual_regen(n, seed, _p(_f64(x)), _p(_f64(b)), _p(r))
     return r
+
+
+def residual_rows(n: int, seed: int, x, b, rows) -> np.ndarray:
+    """r[rows] of r = b - A x, A regenerated (sampled rows of residual_regen)."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    out = np.zeros(len(rows))
+    lib().orc_residual_rows(n, seed, _p(_f64(x)), _p(_f64(b)), rows.ctypes.data_as(ctypes.c_void_p), len(rows),
+                            _p(out))
+    return out
 
 
 def hpl_eta_regen(n: int, seed: int, x, b) -> float:

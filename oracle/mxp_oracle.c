@@ -272,6 +272,23 @@ void orc_residual_regen(int64_t n, uint64_t seed, const double *x, const double 
     }
 }
 
+/* the same residual for the m sampled rows rows[0..m-1] only: out[k] = r[rows[k]] */
+void orc_residual_rows(int64_t n, uint64_t seed, const double *x, const double *b, const int64_t *rows, int64_t m,
+                       double *out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) {
+        const int64_t i = rows[k];
+        double ax = 0.0, dsum = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double a = orc_entry_draw(seed, i, j);
+            dsum += fabs(a);
+            if (j != i) ax += a * x[j];
+        }
+        out[k] = b[i] - (ax + dsum * x[i]);
+    }
+}
+
 /* HPL scaled residual with A regenerated (O(n) memory) */
 double orc_hpl_eta_regen(int64_t n, uint64_t seed, const double *x, const double *b)
 {

@@ -140,3 +140,18 @@ def test_jacobi_regen_matches_lu_and_residual_regen_matches_dense():
     # and a planted error of 1e-10 relative in x is seen identically by both
     xb = xl * (1 + 1e-10)
     assert oracle.hpl_eta_regen(n, seed, xb, b) == pytest.approx(oracle.hpl_eta(A, xb, b), rel=1e-3)
+
+
+def test_residual_rows_are_the_dense_residual_on_the_sampled_rows():
+    # sampled rows of b - A x with A regenerated, against the dense product
+    n, seed = 300, 17
+    A, b = _system(n, seed)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, n)
+    rows = np.array([0, 1, 7, 128, 255, 299] + list(rng.choice(n, 10, replace=False)))
+    got = oracle.residual_rows(n, seed, x, b, rows)
+    want = (b - A @ x)[rows]
+    scale = (np.abs(A) @ np.abs(x) + np.abs(b))[rows]
+    assert np.all(np.abs(got - want) <= 4 * n * 2.0 ** -53 * scale)
+    # the same values as the full regenerated residual, bit for bit
+    assert np.array_equal(got, oracle.residual_regen(n, seed, x, b)[rows])
