@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--store", default="f16")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--scaling", default="none", choices=["none", "row_equil"])
     ap.add_argument("--cpu-n", type=int, default=4608, help="oracle sample size for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-baseline", action="store_true")
@@ -280,7 +281,8 @@ def main():
         prob.A.copy_(A0)                        # untimed input restore
         if timed_events:
             timed_events[0].record(stream)
-        fac = mxp.mxp_factor(prob, nb, args.update, work=fwork, aux=aux)
+        fac = mxp.mxp_factor(prob, nb, args.update, work=fwork, aux=aux,
+                             scaling=mxp.SCALE_ROW_EQUIL if args.scaling == "row_equil" else mxp.SCALE_NONE)
         res = mxp.mxp_solve_ir(prob, fac, restart=args.restart, work=swork, X=X)
         if timed_events:
             timed_events[1].record(stream)
@@ -354,9 +356,10 @@ def main():
         "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.update, "data": "synthetic",
         "config": {"workload": "HPL-MxP solve n=%d nb=%d %s update %s storage, FP32 panel/TRSM, FP64 GMRES-IR "
-                               "restart %d, seed %d" % (n, nb, args.update, args.store, args.restart, args.seed),
+                               "restart %d, seed %d%s" % (n, nb, args.update, args.store, args.restart, args.seed,
+                                                      ", row-equilibrated" if args.scaling == "row_equil" else ""),
                    "n": n, "nb": nb, "update": args.update, "store": args.store, "restart": args.restart,
-                   "nrhs": 1, "parallelism": "single GPU"},
+                   "nrhs": 1, "scaling": args.scaling, "parallelism": "single GPU"},
         "p50_ms": round(statistics.median(step_ms), 3),
         "p99_ms": round(sorted(step_ms)[min(len(step_ms) - 1, int(0.99 * len(step_ms)))], 3),
         "wall_ms_per_step_incl_untimed_restore": round(1e3 * wall / args.steps, 3),

@@ -36,9 +36,7 @@ def _solve(n, nb, update, store, seed, scaling=mxp.SCALE_NONE):
     return prob, fac, res
 
 
-def _free(*objs):
-    for o in objs:
-        del o
+def _release():
     gc.collect()
     torch.cuda.empty_cache()
 
@@ -68,7 +66,8 @@ def test_benchmark_workload_full_size_vs_jacobi_oracle():
     assert res.status[0] == mxp.OK and res.eta[0] < 16 and res.iters[0] <= 50
     x = res.X[0].cpu().numpy()
     b = prob.B[0].cpu().numpy()
-    _free(fac)
+    del fac
+    _release()
     xj, sweeps = oracle.jacobi_regen(n, seed, b, max_sweeps=60)
     assert sweeps < 60
     err = np.abs(x - xj).max() / np.abs(xj).max()
@@ -76,7 +75,6 @@ def test_benchmark_workload_full_size_vs_jacobi_oracle():
           flush=True)
     assert err <= 1e-12
     assert oracle.hpl_eta_regen(n, seed, x, b) < 16
-    _free(prob, res)
 
 
 @pytest.mark.parametrize("update", ["bf16", "f16"])
@@ -86,10 +84,12 @@ def test_large_config_bf16_fp16_scaled_and_unscaled(update, scaling):
     print("full size n=%d nb=%d %s scaling=%d" % (n, nb, update, scaling), flush=True)
     prob, fac, res = _solve(n, nb, update, update, seed, scaling)
     assert res.status[0] == mxp.OK and res.eta[0] < 16 and res.iters[0] <= 50
-    _free(fac)
+    del fac
+    _release()
     worst = _check_sampled_rows(prob, res.X[0])
     print("  iters %d eta %.3g, sampled-row eta %.3g" % (res.iters[0], res.eta[0], worst), flush=True)
-    _free(prob, res)
+    del prob, res
+    _release()
 
 
 def test_fp8_config_full_size():
@@ -97,7 +97,9 @@ def test_fp8_config_full_size():
     print("full size n=%d nb=%d f8/f16" % (n, nb), flush=True)
     prob, fac, res = _solve(n, nb, "f8", "f16", seed)
     assert res.status[0] == mxp.OK and res.eta[0] < 16 and res.iters[0] <= 50
-    _free(fac)
+    del fac
+    _release()
     worst = _check_sampled_rows(prob, res.X[0])
     print("  iters %d eta %.3g, sampled-row eta %.3g" % (res.iters[0], res.eta[0], worst), flush=True)
-    _free(prob, res)
+    del prob, res
+    _release()
