@@ -4,7 +4,7 @@
 // before the 16-bit trailing update).
 //
 // The block is at most 1024 x 1024 and its factorisation is a chain of small
-// dependent steps, so one work-group of eight waves owns it from start to
+// dependent steps, so one work-group of four waves owns it from start to
 // end: no launch gaps, no competition with the trailing update for the
 // dispatcher, and every intermediate result stays in the CU's L1/LDS or the
 // XCD's L2.  The block is copied to an FP32 workspace T (column-major,
@@ -14,7 +14,7 @@
 //     phase L: waves 0 and 1 each apply the last update to tile (t,t) and
 //              factor it in registers (row r of the tile in lane r); wave 0
 //              then forms the inverse of its unit-lower factor, wave 1 that
-//              of its upper factor.  Waves 2..7 (and 0, 1 once done) apply
+//              of its upper factor.  Waves 2, 3 (and 0, 1 once done) apply
 //              update t-1 to every other trailing tile.
 //     phase T: tiles (i,t) <- tile(i,t) U_tt^-1 and (t,j) <- L_tt^-1 tile(t,j)
 //
@@ -35,7 +35,10 @@ namespace {
 typedef float f16v_t __attribute__((ext_vector_type(16)));
 typedef float v32f __attribute__((ext_vector_type(32)));
 
-constexpr int DW = 8;              // waves of the work-group
+// four waves (one per SIMD, at most 256 registers each, 42 KB of LDS): the
+// work-group then fits on a CU beside one work-group of the concurrent trailing
+// update instead of waiting for a whole CU to drain
+constexpr int DW = 4;              // waves of the work-group
 constexpr int DT = DW * 64;        // threads
 constexpr int TP = 33;             // LDS pitch of a staged 32 x 32 tile (column-major)
 constexpr int TILE_F = 32 * TP;    // floats of one staged tile
@@ -97,7 +100,7 @@ MXP_DEV int res_colu(int q) { return 8 * (q >> 2) + (q & 3); }
 }  // namespace
 
 template <int ST>
-__global__ __launch_bounds__(DT) void k_diag_lu(typename Store<ST>::T* A, int64_t lda, int64_t k, int kb, int kbp,
+__global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int64_t lda, int64_t k, int kb, int kbp,
                                                 float* __restrict__ T, float* __restrict__ Trm, int ldt,
                                                 float* __restrict__ linv, float* __restrict__ uinv,
                                                 unsigned long long* info) {

@@ -95,11 +95,16 @@ template <> struct Quad<BF16> {
     }
 };
 
-constexpr int GT = 256;           // tile edge
-constexpr int GBK = 128;          // K bytes per stage
-constexpr int GSTG = GT * GBK;    // bytes of one operand stage (XOR-swizzled, unpadded)
-constexpr int GCH = GBK / 16;     // 16-byte chunks per operand row
-constexpr int GGROUP = 8;         // tile rows per group in the tile order
+// Work-group tile TM x TN = 256 x 128, 4 waves in a 2 x 2 grid, each wave
+// 128 x 64 (8 blocks of 32 x 32, accumulators in AGPRs).  Two work-groups
+// share a CU (at most 256 registers per wave, 72 KB of LDS each), so that
+// one work-group's epilogue (HBM-bound) overlaps the other's MFMA loop.
+constexpr int TM = 256, TN = 128;
+constexpr int GBK = 64;            // K bytes per stage
+constexpr int NBUF = 3;            // stages in LDS: two copies in flight while one is read
+constexpr int GCH = GBK / 16;      // 16-byte chunks per operand row
+constexpr int SA = TM * GBK, SB = TN * GBK;   // bytes of one A / B stage
+constexpr int GGROUP = 8;          // tile rows per group in the tile order
 
 // Direct global->LDS copy of 16 bytes per lane: lane L lands at l + 16 L
 // (l is wave-uniform).  gfx950 global_load_lds_dwordx4.
@@ -107,8 +112,8 @@ MXP_DEV void dma16(const char* g, char* l) {
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
                                      (void __attribute__((address_space(3)))*)l, 16, 0, 0);
 }
-// s_waitcnt vmcnt(0) (expcnt / lgkmcnt not waited)
-MXP_DEV void wait_vm0() { __builtin_amdgcn_s_waitcnt((0x7 << 4) | (0xF << 8)); }
+// s_waitcnt vmcnt(N) (expcnt / lgkmcnt not waited); N < 16
+template <int N> MXP_DEV void wait_vm() { __builtin_amdgcn_s_waitcnt((N & 0xF) | (0x7 << 4) | (0xF << 8)); }
 
 // byte offset of (row, byte b) in an operand stage: 16-byte chunks XOR-swizzled by row
 MXP_DEV int swz(int row, int b) { return row * GBK + ((((b >> 4) ^ (row & (GCH - 1))) << 4) | (b & 15)); }
@@ -142,44 +147,43 @@ template <> struct Frag<F8> {
     }
 };
 
-// Tile 256 x 256, 256 threads = 4 waves in a 2 x 2 grid, each wave 128 x 128
-// (16 blocks of 32 x 32; accumulators in AGPRs).  Operands: K-major rows,
-// copied 128 bytes of K per stage straight into two XOR-swizzled LDS
-// buffers (no staging registers); the fragments of k-step ks+1 are read
-// from LDS while the 16 MFMAs of k-step ks run.  Epilogue, full tiles with
-// 16-bit C: the freed LDS holds the C tile (read and written with 1 KB
-// coalesced accesses), updated in place in the MFMA layout; other tiles
-// update C directly with guarded accesses.
+// Operands: K-major rows, copied GBK bytes of K per stage straight into
+// XOR-swizzled LDS buffers (no staging registers), NBUF stages deep; the
+// fragments of k-step ks+1 are read from LDS while the MFMAs of k-step ks
+// run.  Epilogue, full tiles with 16-bit C: the freed LDS holds the C tile
+// (read and written with coalesced 16-byte accesses, 512 bytes per column),
+// updated in place in the MFMA layout; other tiles update C directly with
+// guarded accesses.
 template <int OP, int ST>
-__global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, int64_t ldc, int64_t M, int64_t N,
-                                                     int K, const char* __restrict__ Aq, const char* __restrict__ Bq,
-                                                     const float* __restrict__ inv_sa,
-                                                     const float* __restrict__ inv_sb, int tiles_m, int tiles_n,
-                                                     int per_xcd, int slots, int vec_ok) {
+__global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C, int64_t ldc, int64_t M, int64_t N,
+                                                        int K, const char* __restrict__ Aq,
+                                                        const char* __restrict__ Bq,
+                                                        const float* __restrict__ inv_sa,
+                                                        const float* __restrict__ inv_sb, int tiles_m, int tiles_n,
+                                                        int per_xcd, int vec_ok) {
     typedef typename Store<ST>::T CT;
     typedef typename Frag<OP>::T FT;
     constexpr int KB = Mfma<OP>::KB;
     constexpr int NKS = GBK / KB;          // k-steps per stage
     constexpr int RPI = 64 / GCH;          // operand rows per 1 KB copy instruction
-    constexpr int NI = GT / RPI / 4;       // copy instructions per wave, per operand and stage
-    constexpr int CP = GT * (int)sizeof(CT) + 16;  // LDS pitch of a C column in the epilogue
+    constexpr int NIA = TM / RPI / 4, NIB = TN / RPI / 4;   // copy instructions per wave and stage
+    constexpr int NIS = NIA + NIB;
+    constexpr int CP = TM * (int)sizeof(CT) + 16;  // LDS pitch of a C column in the epilogue
     extern __shared__ __attribute__((aligned(16))) char lds[];
     char* sA = lds;
-    char* sB = lds + 2 * GSTG;
+    char* sB = lds + NBUF * SA;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave & 1, wn = wave >> 1;
-    // persistent: work-group j of XCD x (x = blockIdx % 8) walks tiles
-    // x*per_xcd + j, + slots, + 2 slots, ... of its XCD's contiguous range
+    // work-group j of XCD x (x = blockIdx % 8) takes tile x*per_xcd + j of its XCD's contiguous range
     const int xcd = (int)(blockIdx.x % 8);
-    const int xend = min((xcd + 1) * per_xcd, tiles_m * tiles_n);
-    for (int lin = xcd * per_xcd + (int)(blockIdx.x / 8); lin < xend; lin += slots) {
-    __syncthreads();                      // LDS of the previous tile no longer read
+    const int lin = xcd * per_xcd + (int)(blockIdx.x / 8);
+    if (lin >= min((xcd + 1) * per_xcd, tiles_m * tiles_n)) return;
     const int group_size = GGROUP * tiles_n;
     const int first_m = (lin / group_size) * GGROUP;
     const int gm = (tiles_m - first_m) < GGROUP ? (tiles_m - first_m) : GGROUP;
     const int tm = first_m + (lin % group_size) % gm;
     const int tn = (lin % group_size) / gm;
-    const int64_t row0 = (int64_t)tm * GT, col0 = (int64_t)tn * GT;
+    const int64_t row0 = (int64_t)tm * TM, col0 = (int64_t)tn * TN;
     constexpr int eb = sizeof(typename Operand<OP>::T);
     const int64_t Kbytes = (int64_t)K * eb;
     const char* gA = Aq + row0 * Kbytes;
@@ -188,87 +192,101 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, i
     const int lr = lane & 31, lh = lane >> 5;
     const int l_row = lane / GCH, l_pch = lane % GCH;
     auto issue = [&](int st) {
-        const int buf = st & 1;
+        const int buf = st % NBUF;
 #pragma unroll
-        for (int i = 0; i < NI; ++i) {
-            const int j = wave * NI + i;                      // 1 KB slice of the stage
+        for (int i = 0; i < NIA; ++i) {
+            const int j = wave * NIA + i;                     // 1 KB slice of the stage
             const int row = j * RPI + l_row;
             const int lch = l_pch ^ (row & (GCH - 1));        // logical chunk stored at this lane's slot
-            const int64_t go = (int64_t)row * Kbytes + (int64_t)st * GBK + lch * 16;
-            dma16(gA + go, sA + buf * GSTG + j * 1024);
-            dma16(gB + go, sB + buf * GSTG + j * 1024);
+            dma16(gA + (int64_t)row * Kbytes + (int64_t)st * GBK + lch * 16, sA + buf * SA + j * 1024);
+        }
+#pragma unroll
+        for (int i = 0; i < NIB; ++i) {
+            const int j = wave * NIB + i;
+            const int row = j * RPI + l_row;
+            const int lch = l_pch ^ (row & (GCH - 1));
+            dma16(gB + (int64_t)row * Kbytes + (int64_t)st * GBK + lch * 16, sB + buf * SB + j * 1024);
         }
     };
-    f16v acc[4][4];
+    f16v acc[4][2];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    issue(0);
+#pragma unroll
+    for (int st = 0; st < NBUF - 1; ++st)
+        if (st < nst) issue(st);
     for (int st = 0; st < nst; ++st) {
-        wait_vm0();
-        __syncthreads();                  // stage st visible; stage st-1's buffer free
-        if (st + 1 < nst) issue(st + 1);
-        const char* A0 = sA + (st & 1) * GSTG;
-        const char* B0 = sB + (st & 1) * GSTG;
-        FT ac[4], bc[4];
+        // stage st has landed when at most the younger stage's copies are outstanding
+        if (st + 1 < nst) wait_vm<NIS>();
+        else wait_vm<0>();
+        __syncthreads();                  // stage st visible to all; stage st-1's buffer free
+        if (st + NBUF - 1 < nst) issue(st + NBUF - 1);
+        const char* A0 = sA + (st % NBUF) * SA;
+        const char* B0 = sB + (st % NBUF) * SB;
+        FT ac[4], bc[2];
 #pragma unroll
         for (int a = 0; a < 4; ++a) ac[a] = Frag<OP>::ld(A0, wm * 128 + a * 32 + lr, lh * (KB / 2));
 #pragma unroll
-        for (int b = 0; b < 4; ++b) bc[b] = Frag<OP>::ld(B0, wn * 128 + b * 32 + lr, lh * (KB / 2));
+        for (int b = 0; b < 2; ++b) bc[b] = Frag<OP>::ld(B0, wn * 64 + b * 32 + lr, lh * (KB / 2));
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
-            FT an[4], bn[4];
+            FT an[4], bn[2];
             if (ks + 1 < NKS) {
                 const int boff = (ks + 1) * KB + lh * (KB / 2);
 #pragma unroll
                 for (int a = 0; a < 4; ++a) an[a] = Frag<OP>::ld(A0, wm * 128 + a * 32 + lr, boff);
 #pragma unroll
-                for (int b = 0; b < 4; ++b) bn[b] = Frag<OP>::ld(B0, wn * 128 + b * 32 + lr, boff);
+                for (int b = 0; b < 2; ++b) bn[b] = Frag<OP>::ld(B0, wn * 64 + b * 32 + lr, boff);
             }
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) acc[a][b] = Frag<OP>::mma(ac[a], bc[b], acc[a][b]);
+                for (int b = 0; b < 2; ++b) acc[a][b] = Frag<OP>::mma(ac[a], bc[b], acc[a][b]);
             if (ks + 1 < NKS) {
                 // interleave the LDS reads of the next k-step with these MFMAs
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                for (int q = 0; q < 6; ++q) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
                     __builtin_amdgcn_sched_group_barrier(0x100, OP == F8 ? 2 : 1, 0);
                 }
 #pragma unroll
                 for (int a = 0; a < 4; ++a) ac[a] = an[a];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) bc[b] = bn[b];
+                for (int b = 0; b < 2; ++b) bc[b] = bn[b];
             }
         }
     }
-    const bool full = vec_ok && (row0 + GT <= M) && (col0 + GT <= N);
+    const bool full = vec_ok && (row0 + TM <= M) && (col0 + TN <= N);
     if constexpr (sizeof(CT) == 2) {
         if (full) {
-            constexpr int COLB = GT * 2;           // bytes of a tile column
+            constexpr int COLB = TM * 2;           // bytes of a tile column
             constexpr int LPC = COLB / 16;         // lanes per column
             constexpr int CPI = 64 / LPC;          // columns per wave instruction
-            constexpr int NIT = GT / 4 / CPI;      // instructions per wave
+            constexpr int NIT = TN / 4 / CPI;      // instructions per wave
             const int lc = lane / LPC, lo = (lane % LPC) * 16;
             __syncthreads();                       // operand buffers no longer read
-#pragma unroll 8
+            i4v xv[NIT];
+#pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int c = (wave * NIT + it) * CPI + lc;
-                i4v x = __builtin_nontemporal_load((const i4v*)((const char*)(C + row0 + (col0 + c) * ldc) + lo));
-                *(i4v*)(lds + c * CP + lo) = x;
+                xv[it] = __builtin_nontemporal_load((const i4v*)((const char*)(C + row0 + (col0 + c) * ldc) + lo));
+            }
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                const int c = (wave * NIT + it) * CPI + lc;
+                *(i4v*)(lds + c * CP + lo) = xv[it];
             }
             __syncthreads();
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 const float ia = inv_sa[(row0 + wm * 128 + a * 32) / 32];
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const float d = ia * inv_sb[(col0 + wn * 128 + b * 32) / 32];
-                    const int c = wn * 128 + b * 32 + lr;
+                for (int b = 0; b < 2; ++b) {
+                    const float d = ia * inv_sb[(col0 + wn * 64 + b * 32) / 32];
+                    const int c = wn * 64 + b * 32 + lr;
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
                         CT* p = (CT*)(lds + c * CP) + wm * 128 + a * 32 + 8 * g + 4 * lh;
@@ -281,13 +299,13 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, i
                 }
             }
             __syncthreads();
-#pragma unroll 8
+#pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 const int c = (wave * NIT + it) * CPI + lc;
                 i4v x = *(const i4v*)(lds + c * CP + lo);
                 __builtin_nontemporal_store(x, (i4v*)((char*)(C + row0 + (col0 + c) * ldc) + lo));
             }
-            continue;
+            return;
         }
     }
     // direct epilogue (FP32 storage, edge tiles): C - acc * d, quads of 4 rows
@@ -296,8 +314,8 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, i
         const int64_t rb = row0 + wm * 128 + a * 32;
         const float ia = inv_sa[rb / 32];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const int64_t cb = col0 + wn * 128 + b * 32;
+        for (int b = 0; b < 2; ++b) {
+            const int64_t cb = col0 + wn * 64 + b * 32;
             const float d = ia * inv_sb[cb / 32];
             const int64_t col = cb + lr;
             if (col >= N) continue;
@@ -319,10 +337,11 @@ __global__ __launch_bounds__(256) void k_gemm_update(typename Store<ST>::T* C, i
             }
         }
     }
-    }  // tile loop
 }
 
-static constexpr int gemm_lds_bytes() { return 4 * GSTG > GT * (GT * 2 + 16) ? 4 * GSTG : GT * (GT * 2 + 16); }
+static constexpr int gemm_lds_bytes() {
+    return NBUF * (SA + SB) > TN * (TM * 2 + 16) ? NBUF * (SA + SB) : TN * (TM * 2 + 16);
+}
 
 template <int OP, int ST>
 static hipError_t gemm_typed(void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq, const void* Bq,
@@ -330,17 +349,14 @@ static hipError_t gemm_typed(void* C, int64_t ldc, int64_t M, int64_t N, int K, 
     static const hipError_t attr = hipFuncSetAttribute((const void*)k_gemm_update<OP, ST>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, gemm_lds_bytes());
     if (attr) return attr;
-    const int tm = (int)((M + GT - 1) / GT), tn = (int)((N + GT - 1) / GT);
+    const int tm = (int)((M + TM - 1) / TM), tn = (int)((N + TN - 1) / TN);
     const int nt = tm * tn;
     const int per_xcd = (nt + 7) / 8;
-    // one work-group per tile: the dispatcher then interleaves work-groups of
-    // kernels on other streams as tiles retire
-    const int slots = per_xcd;
     // vectorised C access needs 16-byte aligned columns
     const int vec_ok = ((ldc * (int64_t)sizeof(typename Store<ST>::T)) % 16 == 0 && (((uintptr_t)C) % 16) == 0) ? 1 : 0;
-    k_gemm_update<OP, ST><<<8 * slots, 256, gemm_lds_bytes(), s>>>((typename Store<ST>::T*)C, ldc, M, N, K,
-                                                              (const char*)Aq, (const char*)Bq, inv_sa, inv_sb, tm,
-                                                              tn, per_xcd, slots, vec_ok);
+    k_gemm_update<OP, ST><<<8 * per_xcd, 256, gemm_lds_bytes(), s>>>((typename Store<ST>::T*)C, ldc, M, N, K,
+                                                                (const char*)Aq, (const char*)Bq, inv_sa, inv_sb,
+                                                                tm, tn, per_xcd, vec_ok);
     return hipGetLastError();
 }
 
