@@ -65,7 +65,7 @@ hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t 
 // concurrent factorisations need a context each.
 struct Lookahead {
     hipStream_t side = nullptr;
-    hipEvent_t ev_cross = nullptr, ev_panel = nullptr;
+    hipEvent_t ev_diag = nullptr, ev_cross = nullptr, ev_panel = nullptr;
 };
 hipError_t lookahead_create(Lookahead* la);
 void lookahead_destroy(Lookahead* la);

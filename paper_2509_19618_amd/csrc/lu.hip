@@ -240,14 +240,13 @@ static inline size_t trsm_smem(int nb) { return (size_t)(SR * (nb + 1) + 2 * 16 
 // scales; writes the operand Lq (K-major, update format, scaled), the stored
 // L21 (storage format, scaled) and the scales.
 template <int ST, int OP>
-__global__ __launch_bounds__(256) void k_trsm_L(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
-                                                const float* __restrict__ Urm, const float* __restrict__ uinv,
-                                                typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk) {
-    extern __shared__ float smem[];
+__device__ void trsm_L_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
+                             const float* __restrict__ Urm, const float* __restrict__ uinv,
+                             typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk, float* smem, int w) {
     const int SP = nb + 1;
     float* S = smem;
     float* red = smem + SR * SP;
-    const int tid = threadIdx.x, w = blockIdx.x;
+    const int tid = threadIdx.x;
     const int64_t r0 = k + nb + (int64_t)SR * w;
     int64_t rv = n - r0;
     rv = rv > SR ? SR : (rv < 0 ? 0 : rv);
@@ -277,14 +276,13 @@ __global__ __launch_bounds__(256) void k_trsm_L(typename Store<ST>::T* A, int64_
 // U12 strip: Y (nb x 32) = L11^-1 A12[:, cols]; operand Uq (K-major: column
 // j has nb contiguous values) scaled, stored U12 unscaled.
 template <int ST, int OP>
-__global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
-                                                const float* __restrict__ T, const float* __restrict__ linv,
-                                                typename Operand<OP>::T* Uq, float* inv_sb) {
-    extern __shared__ float smem[];
+__device__ void trsm_U_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
+                             const float* __restrict__ T, const float* __restrict__ linv,
+                             typename Operand<OP>::T* Uq, float* inv_sb, float* smem, int w) {
     const int SP = nb + 1;
     float* S = smem;
     float* red = smem + SR * SP;
-    const int tid = threadIdx.x, w = blockIdx.x;
+    const int tid = threadIdx.x;
     const int64_t c0 = k + nb + (int64_t)SR * w;
     int64_t cv = n - c0;
     cv = cv > SR ? SR : (cv < 0 ? 0 : cv);
@@ -302,6 +300,20 @@ __global__ __launch_bounds__(256) void k_trsm_U(typename Store<ST>::T* A, int64_
         Uq[((int64_t)SR * w + cc) * nb + kk] = Operand<OP>::from_f32(S[cc * SP + kk] * s_op);
         if (cc < cv) A[(k + kk) + (c0 + cc) * lda] = Store<ST>::from_f32(S[cc * SP + kk]);
     }
+}
+
+// Both strip solves of one block step in one launch: work-groups [0, nstrip)
+// solve the L21 strips, [nstrip, 2 nstrip) the U12 strips (independent).
+template <int ST, int OP>
+__global__ __launch_bounds__(256) void k_trsm(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
+                                              int nstrip, const float* __restrict__ Urm, const float* __restrict__ uinv,
+                                              const float* __restrict__ T, const float* __restrict__ linv,
+                                              typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk,
+                                              typename Operand<OP>::T* Uq, float* inv_sb) {
+    extern __shared__ float smem[];
+    const int w = (int)blockIdx.x;
+    if (w < nstrip) trsm_L_strip<ST, OP>(A, lda, n, k, nb, Urm, uinv, Lq, inv_sa, lsc_blk, smem, w);
+    else trsm_U_strip<ST, OP>(A, lda, n, k, nb, T, linv, Uq, inv_sb, smem, w - nstrip);
 }
 
 // Full inverses of the diagonal blocks (for the preconditioner), all blocks
@@ -362,6 +374,7 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
 hipError_t lookahead_create(Lookahead* la) {
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&la->side, hipStreamNonBlocking))) return e;
+    if ((e = hipEventCreateWithFlags(&la->ev_diag, hipEventDisableTiming))) return e;
     if ((e = hipEventCreateWithFlags(&la->ev_cross, hipEventDisableTiming))) return e;
     return hipEventCreateWithFlags(&la->ev_panel, hipEventDisableTiming);
 }
@@ -369,6 +382,7 @@ hipError_t lookahead_create(Lookahead* la) {
 void lookahead_destroy(Lookahead* la) {
     if (la->ev_panel) hipEventDestroy(la->ev_panel);
     if (la->ev_cross) hipEventDestroy(la->ev_cross);
+    if (la->ev_diag) hipEventDestroy(la->ev_diag);
     if (la->side) hipStreamDestroy(la->side);
     *la = Lookahead();
 }
@@ -402,9 +416,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     typedef typename Operand<OP>::T OP_T;
     static const hipError_t attr = []() {
         hipError_t e2;
-        if ((e2 = hipFuncSetAttribute((const void*)k_trsm_L<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)trsm_smem(1024)))) return e2;
-        if ((e2 = hipFuncSetAttribute((const void*)k_trsm_U<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+        if ((e2 = hipFuncSetAttribute((const void*)k_trsm<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)trsm_smem(1024)))) return e2;
         if ((e2 = hipFuncSetAttribute((const void*)k_inv_upper, hipFuncAttributeMaxDynamicSharedMemorySize,
                                       (int)trsm_smem(1024)))) return e2;
@@ -446,11 +458,11 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         const int nstrip = (int)(rup(m, 256) / SR);
         const size_t smem = trsm_smem(nb);
         hipEvent_t pt = prof::begin(st);
-        k_trsm_L<ST, OP><<<nstrip, 256, smem, st>>>(A, lda, n, k, nb, p.Trm + blk * nb * nb,
-                                                    p.uinv + blk * nb * 64, (OP_T*)p.Lq + set * opset,
-                                                    p.inv_sa + set * scset, p.lsc + blk * nstrips_total);
-        k_trsm_U<ST, OP><<<nstrip, 256, smem, st>>>(A, lda, n, k, nb, p.T + blk * nb * nb, p.linv + blk * nb * 64,
-                                                    (OP_T*)p.Uq + set * opset, p.inv_sb + set * scset);
+        k_trsm<ST, OP><<<2 * nstrip, 256, smem, st>>>(A, lda, n, k, nb, nstrip, p.Trm + blk * nb * nb,
+                                                       p.uinv + blk * nb * 64, p.T + blk * nb * nb,
+                                                       p.linv + blk * nb * 64, (OP_T*)p.Lq + set * opset,
+                                                       p.inv_sa + set * scset, p.lsc + blk * nstrips_total,
+                                                       (OP_T*)p.Uq + set * opset, p.inv_sb + set * scset);
         prof::end(pt, prof::TRSM, st, 2.0 * m * (double)nb * nb,
                   4.0 * m * (double)nb * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
         return hipGetLastError();
@@ -471,15 +483,11 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
                   2.0 * M * (double)N * sizeof(ST_T) + (M + N) * (double)nb * sizeof(OP_T));
         return e2;
     };
-    // part: 0 = the whole trailing matrix, 1 = block column and block row k+1, 2 = the rest
+    // part: 0 = the whole trailing matrix, 2 = all but block column and row k+1
     auto update = [&](int64_t k, int part, hipStream_t st) -> hipError_t {
         const int64_t m = n - k - nb;
         const int64_t c = nb;                       // width of block column / row k+1
         if (part == 0) return gemm(k, 0, 0, m, m, st);
-        if (part == 1) {
-            hipError_t e2 = gemm(k, 0, 0, m, c, st);                    // block column
-            return e2 ? e2 : gemm(k, 0, c, c, m - c, st);              // block row
-        }
         return gemm(k, c, c, m - c, m - c, st);
     };
 
@@ -489,12 +497,18 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     for (int64_t k = 0; k + nb < n; k += nb) {
         const int64_t m = n - k - nb;               // trailing size after step k
         if (m > nb) {
-            // cross part, then the next panel (diagonal block and both strip
-            // TRSMs) on the side stream while the main stream updates the rest
-            if ((e = update(k, 1, s))) return e;
+            // the next diagonal block first, so that its LU starts on the side
+            // stream at once; then the rest of block column and row k+1, which
+            // the next strip TRSMs need; the main stream goes on with the rest
+            const int64_t c = nb;
+            if ((e = gemm(k, 0, 0, c, c, s))) return e;
+            if ((e = hipEventRecord(LA->ev_diag, s))) return e;
+            if ((e = hipStreamWaitEvent(LA->side, LA->ev_diag, 0))) return e;
+            if ((e = diag(k + nb, LA->side))) return e;
+            if ((e = gemm(k, c, 0, m - c, c, s))) return e;
+            if ((e = gemm(k, 0, c, c, m - c, s))) return e;
             if ((e = hipEventRecord(LA->ev_cross, s))) return e;
             if ((e = hipStreamWaitEvent(LA->side, LA->ev_cross, 0))) return e;
-            if ((e = diag(k + nb, LA->side))) return e;
             if ((e = trsm(k + nb, LA->side))) return e;
             if ((e = hipEventRecord(LA->ev_panel, LA->side))) return e;
             if ((e = update(k, 2, s))) return e;
