@@ -89,10 +89,12 @@ static FactorPlan make_plan(int64_t n, int64_t nb, int update, int store, void* 
         p.inv_sa = (float*)(w + wl.inv_sa);
         p.inv_sb = (float*)(w + wl.inv_sb);
         p.info = (unsigned long long*)(w + wl.info);
+        p.dsync = (int*)(w + wl.dsync);
     } else {
         p.Lq = p.Uq = nullptr;
         p.inv_sa = p.inv_sb = nullptr;
         p.info = nullptr;
+        p.dsync = nullptr;
     }
     return p;
 }
@@ -125,6 +127,10 @@ int factor_with(int64_t n, int64_t nb, int update, int store, int scaling, const
         HIPCHK(hipMemcpyAsync(&v, p.info, 8, hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         *info = (v == ~0ull) ? 0 : (int64_t)v;
+        if (*info == (1ll << 62)) {
+            *info = 0;
+            return set_err(MXP_EHIP, "mxp_factor: a wait of the diagonal-block LU expired%s", "");
+        }
         if (*info) return MXP_ESINGULAR;
     }
     return MXP_OK;

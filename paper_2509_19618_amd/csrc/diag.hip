@@ -1,22 +1,32 @@
-// diag.hip -- FP32 LU without pivoting of one diagonal block, in a single
-// work-group (the panel factorisation of the right-looking blocked LU,
-// Section 3 "HPL-MxP": the diagonal block is factored in 32-bit arithmetic
-// before the 16-bit trailing update).
+// diag.hip -- FP32 LU without pivoting of one diagonal block (the panel
+// factorisation of the right-looking blocked LU, Section 3 "HPL-MxP": the
+// diagonal block is factored in 32-bit arithmetic before the 16-bit
+// trailing update).
 //
 // The block is at most 1024 x 1024 and its factorisation is a chain of small
-// dependent steps, so one work-group of four waves owns it from start to
-// end: no launch gaps, no competition with the trailing update for the
-// dispatcher, and every intermediate result stays in the CU's L1/LDS or the
-// XCD's L2.  The block is copied to an FP32 workspace T (column-major,
-// ld = ldt) and factored right-looking over 32 x 32 tiles:
+// dependent steps over 32 x 32 tiles of an FP32 copy T (column-major, ld =
+// ldt), right-looking:
 //
+//   phase load:  T <- A11 (tile tasks)
 //   for t = 0 .. P-1   (P = kbp / 32)
-//     phase L: waves 0 and 1 each apply the last update to tile (t,t) and
-//              factor it in registers (row r of the tile in lane r); wave 0
-//              then forms the inverse of its unit-lower factor, wave 1 that
-//              of its upper factor.  Waves 2, 3 (and 0, 1 once done) apply
-//              update t-1 to every other trailing tile.
-//     phase T: tiles (i,t) <- tile(i,t) U_tt^-1 and (t,j) <- L_tt^-1 tile(t,j)
+//     phase L(t): the leader (waves 0 and 1 of work-group 0) applies the last
+//                 update to tile (t,t) and factors it in registers (row r of
+//                 the tile in lane r), then wave 0 forms the inverse of the
+//                 unit-lower factor and wave 1 that of the upper one; every
+//                 other wave applies update t-1 to the other trailing tiles;
+//     phase T(t): tiles (i,t) <- tile(i,t) U_tt^-1, (t,j) <- L_tt^-1 tile(t,j)
+//   phase asm:   off-diagonal blocks of the 64 x 64 sub-block inverses.
+//
+// One launch of a few work-groups of four waves (each fits on a CU beside a
+// work-group of the concurrent trailing update).  Every wave works on its
+// own: it claims tasks of the current phase from a device-wide counter,
+// counts them done, and the wave that completes a phase opens the next one.
+// Work-groups that start late simply join the current phase, so the leader
+// never waits for a helper to be scheduled.  T and the tile inverses are
+// read and written with device-scope accesses (they go to the device's
+// coherence point), a wave's stores are acknowledged before it counts a task
+// done, and every wait is bounded: on expiry it records an error in *info
+// and the wave exits.
 //
 // Every 32 x 32 x 32 product is one wave's chain of sixteen
 // v_mfma_f32_32x32x2f32.  The kernel also writes the inverses of the 64 x 64
@@ -35,9 +45,9 @@ namespace {
 typedef float f16v_t __attribute__((ext_vector_type(16)));
 typedef float v32f __attribute__((ext_vector_type(32)));
 
-// four waves (one per SIMD, at most 256 registers each, 42 KB of LDS): the
-// work-group then fits on a CU beside one work-group of the concurrent trailing
-// update instead of waiting for a whole CU to drain
+// four waves (one per SIMD, at most 256 registers each, 34 KB of LDS): a
+// work-group then fits on a CU beside one work-group of the concurrent
+// trailing update instead of waiting for a whole CU to drain
 constexpr int DW = 4;              // waves of the work-group
 constexpr int DT = DW * 64;        // threads
 constexpr int TP = 33;             // LDS pitch of a staged 32 x 32 tile (column-major)
@@ -52,12 +62,17 @@ MXP_DEV int opaque(int v) {
 
 MXP_DEV float rl(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 
+// device-scope accesses of data shared between work-groups
+MXP_DEV float gld(const float* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MXP_DEV void gst(float* p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+MXP_DEV int ild(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
 // s[c*TP + r] = g[r + c*ld] for r, c < 32 (lanes along r: coalesced)
 MXP_DEV void stage_cm(float* s, const float* g, int64_t ld) {
     const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
     float v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = g[(int64_t)(2 * q) * ld + (r + h * (int)ld)];
+    for (int q = 0; q < 16; ++q) v[q] = gld(g + (int64_t)(2 * q) * ld + (r + h * (int)ld));
 #pragma unroll
     for (int q = 0; q < 16; ++q) s[(2 * q + h) * TP + r] = v[q];
 }
@@ -67,7 +82,7 @@ MXP_DEV void stage_rm(float* s, const float* g, int64_t ld) {
     const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
     float v[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = g[(int64_t)(2 * q) * ld + (c + h * (int)ld)];
+    for (int q = 0; q < 16; ++q) v[q] = gld(g + (int64_t)(2 * q) * ld + (c + h * (int)ld));
 #pragma unroll
     for (int q = 0; q < 16; ++q) s[c * TP + 2 * q + h] = v[q];
 }
@@ -97,30 +112,47 @@ MXP_DEV int res_col(int q, int lh) { return 8 * (q >> 2) + 4 * lh + (q & 3); }
 // uniform part of res_col
 MXP_DEV int res_colu(int q) { return 8 * (q >> 2) + (q & 3); }
 
+// phases of one diagonal-block LU and their sizes (see the file comment)
+constexpr int NPMAX = 2 * 32 + 2;   // phases for kbp <= 1024
+MXP_DEV int phase_claims(int ph, int P) {
+    if (ph == 0) return P * P;                         // load
+    if (ph == 2 * P + 1) return P;                     // inverse assembly
+    const int t = (ph - 1) / 2;
+    if ((ph - 1) % 2 == 0) return t > 0 ? (P - t) * (P - t) - 1 : 0;   // L(t): updates of step t-1
+    return 2 * (P - 1 - t);                            // T(t)
+}
+// completions that close a phase: its claims, plus the two leaf waves in L(t)
+MXP_DEV int phase_target(int ph, int P) {
+    const bool lphase = ph >= 1 && ph <= 2 * P && (ph - 1) % 2 == 0;
+    return phase_claims(ph, P) + (lphase ? 2 : 0);
+}
+
 }  // namespace
 
 template <int ST>
 __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int64_t lda, int64_t k, int kb, int kbp,
                                                 float* __restrict__ T, float* __restrict__ Trm, int ldt,
-                                                float* __restrict__ linv, float* __restrict__ uinv,
+                                                float* __restrict__ linv, float* __restrict__ uinv, int* sync,
                                                 unsigned long long* info) {
     extern __shared__ __attribute__((aligned(16))) float dsm[];
-    __shared__ int s_cnt[2];
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int lr = lane & 31, lh = lane >> 5;
     float* sA = dsm + (2 * wave) * TILE_F;       // two staging tiles per wave
     float* sB = sA + TILE_F;
-    float* sLinv = dsm + 2 * DW * TILE_F;        // inverses of the current tile's factors
-    float* sUinv = sLinv + TILE_F;
     const int P = kbp / 32;
+    const int NP = 2 * P + 2;
+    int* phase = sync;                           // the open phase (NP = finished)
+    int* claims = sync + 1;
+    int* dones = sync + 1 + NPMAX;
+    const bool leader = blockIdx.x == 0 && wave < 2;
     auto Tt = [&](int I, int J) -> float* { return T + 32 * I + (int64_t)(32 * J) * ldt; };
     const int offA = lr + lh * ldt;          // lane offset of operand element (lr, 2 k2 + lh) of a T tile
     const int offC = lr + 4 * lh * ldt;      // lane offset of result element (lr, res_col(q))
     // operand fetchers: P[lr][k] of a T tile, P and Q of a staged LDS tile
-    auto gP = [&](const float* G) { return [=](int k2) { return G[(int64_t)(2 * k2) * ldt + offA]; }; };
-    auto sP = [&](const float* S) { return [=](int k2) { return S[(2 * k2 + lh) * TP + lr]; }; };
+    auto gP = [&](const float* G) { return [=](int k2) { return gld(G + (int64_t)(2 * k2) * ldt + offA); }; };
     auto sQ = [&](const float* S) { return [=](int k2) { return S[lr * TP + 2 * k2 + lh]; }; };
-    auto Cp = [&](float* G, int q) -> float& { return G[(int64_t)res_colu(q) * ldt + offC]; };
+    auto sP = [&](const float* S) { return [=](int k2) { return S[(2 * k2 + lh) * TP + lr]; }; };
+    auto Cp = [&](float* G, int q) -> float* { return G + (int64_t)res_colu(q) * ldt + offC; };
     // a final tile (I,J), held column-major in the LDS buffer S: to A in the
     // storage format and, transposed, to Trm (both with coalesced stores)
     auto store_final = [&](int I, int J, const float* S) {
@@ -132,38 +164,189 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
             Trm[(32 * J + lr) + (int64_t)(32 * I + 2 * q + lh) * ldt] = S[lr * TP + 2 * q + lh];
         }
     };
-    auto claim = [&](int which) -> int {
+    auto fail = [&]() {
+        if (lane == 0) atomicMin(info, 1ull << 62);
+    };
+    // bounded wait until the open phase is at least ph
+    auto wait_phase = [&](int ph) -> bool {
+        unsigned it = 0;
+        while (ild(phase) < ph) {
+            if (++it > (1u << 26)) {
+                fail();
+                return false;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        return true;
+    };
+    // this wave's stores are acknowledged, then one more completion of ph; the
+    // completion that closes the phase opens the next non-empty one
+    auto complete = [&](int ph) {
+        __builtin_amdgcn_s_waitcnt(0);
+        int old = 0;
+        if (lane == 0) old = atomicAdd(&dones[ph], 1);
+        old = __builtin_amdgcn_readfirstlane(old);
+        if (old + 1 == phase_target(ph, P)) {
+            // T(P-1) is the only empty phase
+            const int nx = (ph + 1 == 2 * P) ? ph + 2 : ph + 1;
+            if (lane == 0) __hip_atomic_store(phase, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    };
+    auto claim = [&](int ph) -> int {
         int v = 0;
-        if (lane == 0) v = atomicAdd(&s_cnt[which], 1);
+        if (lane == 0) v = atomicAdd(&claims[ph], 1);
         return __builtin_amdgcn_readfirstlane(v);
     };
 
-    // ---- load: T <- A11 in FP32, padded with the identity
-    if (tid == 0) s_cnt[0] = s_cnt[1] = 0;
-    typedef typename Store<ST>::T ET;
-    constexpr int RPL = 16 / (int)sizeof(ET);                // rows per 16-byte load
-    const ET* A0 = A + k + k * lda;
-    if (kb == kbp && (lda * (int64_t)sizeof(ET)) % 16 == 0 && ((uintptr_t)A0) % 16 == 0) {
-        // whole columns, 16-byte loads (RPL rows per lane), four columns in flight per wave
-        for (int r0 = RPL * lane; r0 < kbp; r0 += 64 * RPL) {
-            for (int j0 = 4 * wave; j0 < kbp; j0 += 4 * DW) {
-                uint4 raw[4];
+    // the leaf of step t (leader waves only)
+    auto leaf = [&](int t) {
+        // tile (t,t) after the last update, into sA (column-major, pitch TP)
+        if (t == 0) {
+            stage_cm(sA, Tt(0, 0), ldt);
+        } else {
+            stage_cm(sB, Tt(t - 1, t), ldt);
+            const float* Lg = Tt(t, t - 1);
+            const f16v_t acc = prod32(gP(Lg), sQ(sB));
+            float* Cg = Tt(t, t);
 #pragma unroll
-                for (int c = 0; c < 4; ++c) raw[c] = *(const uint4*)(A0 + r0 + (int64_t)(j0 + c) * lda);
+            for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = gld(Cp(Cg, q)) - acc[q];
+        }
+        // LU in registers: lane r (and r + 32) holds row r.  The step loop
+        // stays rolled (small code: the kernel runs once per block, its
+        // instruction cache cold); the step's own column is read through
+        // the register index (s_set_gpr_idx).  Every step sweeps the columns
+        // from the step's range start on for the rows below the pivot: left of
+        // the diagonal a row then holds junk, never read again, and the
+        // multipliers go to sA (column j of L).
+        v32f x;
 #pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const ET* e = (const ET*)&raw[c];
-                    float* dst = T + r0 + (int64_t)(j0 + c) * ldt;
+        for (int c = 0; c < 32; ++c) x[c] = sA[c * TP + lr];
+        float dinv = 0.0f;   // lane j: 1 / U[j][j]
+        auto lu_step = [&](int j, auto C0) {
+            const int lr = opaque(lane & 31);
+            const float xj = x[j];
+            const float rp = __builtin_amdgcn_rcpf(rl(xj, j));   // v_rcp_f32 (1 ulp)
+            dinv = (lr == j) ? rp : dinv;
+            if (lr > j) {
+                // rows at or above the pivot stay as they are (readlane
+                // reads the pivot lane whatever the execution mask)
+                const float l = xj * rp;
 #pragma unroll
-                    for (int m = 0; m < RPL; m += 4)
-                        *(float4*)(dst + m) = make_float4(Store<ST>::load(e, m), Store<ST>::load(e, m + 1),
-                                                          Store<ST>::load(e, m + 2), Store<ST>::load(e, m + 3));
+                for (int c = decltype(C0)::value; c < 32; ++c) x[c] = fmaf(-l, rl(x[c], j), x[c]);
+                if (lh == 0) sA[j * TP + lr] = l;
+            }
+        };
+#pragma unroll 1
+        for (int j = 0; j < 8; ++j) lu_step(j, std::integral_constant<int, 0>());
+#pragma unroll 1
+        for (int j = 8; j < 16; ++j) lu_step(j, std::integral_constant<int, 8>());
+#pragma unroll 1
+        for (int j = 16; j < 24; ++j) lu_step(j, std::integral_constant<int, 16>());
+#pragma unroll 1
+        for (int j = 24; j < 31; ++j) lu_step(j, std::integral_constant<int, 24>());
+        dinv = (lr == 31) ? __builtin_amdgcn_rcpf(rl(x[31], 31)) : dinv;
+        const int o = 32 * (t & 1);
+        float* L64 = linv + (t >> 1) * 4096;   // column-major 64 x 64
+        float* U64 = uinv + (t >> 1) * 4096;   // row-major 64 x 64
+        float X[32];
+        const int lro = opaque(lr);
+#pragma unroll
+        for (int c = 0; c < 32; ++c) X[c] = (c == lro) ? 1.0f : 0.0f;
+        if (wave == 0) {
+            float* Cg = Tt(t, t);
+            if (lh == 0) {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) {
+                    const float f = (c >= lr) ? x[c] : sA[c * TP + lr];
+                    gst(Cg + lr + (int64_t)c * ldt, f);
+                    sB[c * TP + lr] = f;
                 }
             }
+            store_final(t, t, sB);
+            // the pivots are the diagonal of U: report the first zero / non-finite one
+            int bad = -1;
+#pragma unroll
+            for (int c = 31; c >= 0; --c) {
+                const float d = rl(x[c], c);
+                if (32 * t + c < kb && !(d != 0.0f && isfinite(d))) bad = c;
+            }
+            if (bad >= 0 && lane == 0) atomicMin(info, (unsigned long long)(k + 32 * t + bad + 1));
+            // L^-1 by rows: X[i] = e_i - sum_{s<i} L[i][s] X[s]
+            // (row s of X is zero right of s: the sweep stops at C1)
+            auto linv_step = [&](int s2, auto C1) {
+                constexpr int c1 = decltype(C1)::value;
+                const int lr = opaque(lane & 31);
+                if (lr > s2) {
+                    const float l = sA[s2 * TP + lr];
+                    // all broadcasts first (kept apart from the FMAs so that
+                    // the readlane results pipeline instead of alternating)
+                    float pv[c1];
+#pragma unroll
+                    for (int c = 0; c < c1; ++c) pv[c] = rl(X[c], s2);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int c = 0; c < c1; ++c) X[c] = fmaf(-l, pv[c], X[c]);
+                }
+            };
+#pragma unroll 1
+            for (int s2 = 0; s2 < 8; ++s2) linv_step(s2, std::integral_constant<int, 8>());
+#pragma unroll 1
+            for (int s2 = 8; s2 < 16; ++s2) linv_step(s2, std::integral_constant<int, 16>());
+#pragma unroll 1
+            for (int s2 = 16; s2 < 24; ++s2) linv_step(s2, std::integral_constant<int, 24>());
+#pragma unroll 1
+            for (int s2 = 24; s2 < 31; ++s2) linv_step(s2, std::integral_constant<int, 32>());
+            if (lh == 0) {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) {
+                    gst(L64 + (o + lr) + 64 * (o + c), X[c]);
+                    if (o == 0) gst(L64 + lr + 64 * (32 + c), 0.0f);
+                }
+            }
+        } else {
+            // U^-1 by rows, last row first: X[i] = (e_i - sum_{s>i} U[i][s] X[s]) / U[i][i]
+            // (row s of X is zero left of s: the sweep starts at C0)
+            auto uinv_step = [&](int s2, auto C0) {
+                const int lr = opaque(lane & 31);
+                const float sc = (lr == s2) ? dinv : 1.0f;
+#pragma unroll
+                for (int c = decltype(C0)::value; c < 32; ++c) X[c] *= sc;
+                const float w = x[s2];
+                if (lr < s2) {
+                    float pv[32];
+#pragma unroll
+                    for (int c = decltype(C0)::value; c < 32; ++c) pv[c] = rl(X[c], s2);
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int c = decltype(C0)::value; c < 32; ++c) X[c] = fmaf(-w, pv[c], X[c]);
+                }
+            };
+#pragma unroll 1
+            for (int s2 = 31; s2 >= 24; --s2) uinv_step(s2, std::integral_constant<int, 24>());
+#pragma unroll 1
+            for (int s2 = 23; s2 >= 16; --s2) uinv_step(s2, std::integral_constant<int, 16>());
+#pragma unroll 1
+            for (int s2 = 15; s2 >= 8; --s2) uinv_step(s2, std::integral_constant<int, 8>());
+#pragma unroll 1
+            for (int s2 = 7; s2 >= 0; --s2) uinv_step(s2, std::integral_constant<int, 0>());
+            if (lh == 0) {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) sA[c * TP + lr] = X[c];
+            }
+            // row-major copy, read back transposed so that the stores coalesce
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int r = 2 * q + lh;
+                gst(U64 + 64 * (o + r) + o + lr, sA[lr * TP + r]);
+                if (o == 32) gst(U64 + 64 * (32 + r) + lr, 0.0f);
+            }
         }
-    } else {
-        // ragged block: tile by tile, branch-free so that a tile's loads are in flight together
-        for (int u = wave; u < P * P; u += DW) {
+    };
+
+    // one task u of phase ph
+    auto task = [&](int ph, int u) {
+        if (ph == 0) {
+            // load: T tile <- A11 tile in FP32, padded with the identity
             const int I = u % P, J = u / P;
             const int i = 32 * I + lr;
             float v[16];
@@ -175,287 +358,143 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
                 v[q] = in ? v[q] : ((i == j) ? 1.0f : 0.0f);
             }
 #pragma unroll
-            for (int q = 0; q < 16; ++q) T[i + (int64_t)(32 * J + 2 * q + lh) * ldt] = v[q];
+            for (int q = 0; q < 16; ++q) gst(T + i + (int64_t)(32 * J + 2 * q + lh) * ldt, v[q]);
+            return;
         }
-    }
-    __syncthreads();
-
-    for (int t = 0; t < P; ++t) {
-        // ================= phase L(t)
-        if (wave < 2) {
-            // tile (t,t) after the last update, into sA (column-major, pitch TP)
-            if (t == 0) {
-                stage_cm(sA, Tt(0, 0), ldt);
+        if (ph == NP - 1) {
+            if (u < P / 2) {
+                // [L11 0; L21 L22]^-1 = [L11^-1 0; -L22^-1 L21 L11^-1  L22^-1]
+                const int b = u;
+                float* L64 = linv + b * 4096;
+                const float* L21 = Tt(2 * b + 1, 2 * b);
+                stage_cm(sA, L64, 64);
+                const f16v_t y = prod32(gP(L21), sQ(sA));
+#pragma unroll
+                for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = y[q];
+                const float* L22i = L64 + 32 + 64 * 32;
+                const f16v_t x = prod32([=](int k2) { return gld(L22i + 128 * k2 + lr + 64 * lh); }, sQ(sA));
+#pragma unroll
+                for (int q = 0; q < 16; ++q) L64[(32 + lr) + 64 * res_col(q, lh)] = -x[q];
             } else {
-                stage_cm(sB, Tt(t - 1, t), ldt);
-                const float* Lg = Tt(t, t - 1);
-                const f16v_t acc = prod32(gP(Lg), sQ(sB));
-                float* Cg = Tt(t, t);
+                // [U11 U12; 0 U22]^-1 = [U11^-1  -U11^-1 U12 U22^-1; 0 U22^-1]
+                const int b = u - P / 2;
+                float* U64 = uinv + b * 4096;
+                const float* U12 = Tt(2 * b, 2 * b + 1);
+                const float* U22i = U64 + 64 * 32 + 32;
+                const f16v_t z = prod32(gP(U12), [=](int k2) { return gld(U22i + 128 * k2 + 64 * lh + lr); });
 #pragma unroll
-                for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = Cp(Cg, q) - acc[q];
-            }
-            // LU in registers: lane r (and r + 32) holds row r.  The step loop
-            // stays rolled (small code: the kernel runs once per block, its
-            // instruction cache cold); the step's own column is read through
-            // the register index (s_set_gpr_idx).  Every step sweeps all 32
-            // columns of the rows below the pivot: left of the diagonal a row
-            // then holds junk, never read again, and the multipliers go to sA
-            // (column j of L).
-            v32f x;
+                for (int q = 0; q < 16; ++q) sB[res_col(q, lh) * TP + lr] = z[q];
+                stage_rm(sA, U64, 64);
+                const f16v_t x = prod32(sP(sA), sQ(sB));
 #pragma unroll
-            for (int c = 0; c < 32; ++c) x[c] = sA[c * TP + lr];
-            float dinv = 0.0f;   // lane j: 1 / U[j][j]
-            // step j; columns left of C0 are left alone (junk for j >= C0)
-            auto lu_step = [&](int j, auto C0) {
-                const float xj = x[j];
-                const float rp = __builtin_amdgcn_rcpf(rl(xj, j));   // v_rcp_f32 (1 ulp)
-                dinv = (lr == j) ? rp : dinv;
-                if (lr > j) {
-                    // rows at or above the pivot stay as they are (readlane
-                    // reads the pivot lane whatever the execution mask)
-                    const float l = xj * rp;
-#pragma unroll
-                    for (int c = decltype(C0)::value; c < 32; ++c) x[c] = fmaf(-l, rl(x[c], j), x[c]);
-                    if (lh == 0) sA[j * TP + lr] = l;
-                }
-            };
-#pragma unroll 1
-            for (int j = 0; j < 8; ++j) lu_step(j, std::integral_constant<int, 0>());
-#pragma unroll 1
-            for (int j = 8; j < 16; ++j) lu_step(j, std::integral_constant<int, 8>());
-#pragma unroll 1
-            for (int j = 16; j < 24; ++j) lu_step(j, std::integral_constant<int, 16>());
-#pragma unroll 1
-            for (int j = 24; j < 31; ++j) lu_step(j, std::integral_constant<int, 24>());
-            dinv = (lr == 31) ? __builtin_amdgcn_rcpf(rl(x[31], 31)) : dinv;
-            const int o = 32 * (t & 1);
-            float* L64 = linv + (t >> 1) * 4096;   // column-major 64 x 64
-            float* U64 = uinv + (t >> 1) * 4096;   // row-major 64 x 64
-            float X[32];
-            const int lro = opaque(lr);
-#pragma unroll
-            for (int c = 0; c < 32; ++c) X[c] = (c == lro) ? 1.0f : 0.0f;
-            if (wave == 0) {
-                float* Cg = Tt(t, t);
-                if (lh == 0) {
-#pragma unroll
-                    for (int c = 0; c < 32; ++c) {
-                        const float f = (c >= lr) ? x[c] : sA[c * TP + lr];
-                        Cg[lr + (int64_t)c * ldt] = f;
-                        sB[c * TP + lr] = f;
-                    }
-                }
-                store_final(t, t, sB);
-                // the pivots are the diagonal of U: report the first zero / non-finite one
-                int bad = -1;
-#pragma unroll
-                for (int c = 31; c >= 0; --c) {
-                    const float d = rl(x[c], c);
-                    if (32 * t + c < kb && !(d != 0.0f && isfinite(d))) bad = c;
-                }
-                if (bad >= 0 && lane == 0) atomicMin(info, (unsigned long long)(k + 32 * t + bad + 1));
-                // L^-1 by rows: X[i] = e_i - sum_{s<i} L[i][s] X[s]
-                // (row s of X is zero right of s: the sweep stops at C1)
-                auto linv_step = [&](int s2, auto C1) {
-                    constexpr int c1 = decltype(C1)::value;
-                    if (lr > s2) {
-                        const float l = sA[s2 * TP + lr];
-                        // all broadcasts first (kept apart from the FMAs so that
-                        // the readlane results pipeline instead of alternating)
-                        float pv[c1];
-#pragma unroll
-                        for (int c = 0; c < c1; ++c) pv[c] = rl(X[c], s2);
-                        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                        for (int c = 0; c < c1; ++c) X[c] = fmaf(-l, pv[c], X[c]);
-                    }
-                };
-#pragma unroll 1
-                for (int s2 = 0; s2 < 8; ++s2) linv_step(s2, std::integral_constant<int, 8>());
-#pragma unroll 1
-                for (int s2 = 8; s2 < 16; ++s2) linv_step(s2, std::integral_constant<int, 16>());
-#pragma unroll 1
-                for (int s2 = 16; s2 < 24; ++s2) linv_step(s2, std::integral_constant<int, 24>());
-#pragma unroll 1
-                for (int s2 = 24; s2 < 31; ++s2) linv_step(s2, std::integral_constant<int, 32>());
-                if (lh == 0) {
-#pragma unroll
-                    for (int c = 0; c < 32; ++c) {
-                        sLinv[c * TP + lr] = X[c];
-                        L64[(o + lr) + 64 * (o + c)] = X[c];
-                        if (o == 0) L64[lr + 64 * (32 + c)] = 0.0f;
-                    }
-                }
-            } else {
-                // U^-1 by rows, last row first: X[i] = (e_i - sum_{s>i} U[i][s] X[s]) / U[i][i]
-                // (row s of X is zero left of s: the sweep starts at C0)
-                auto uinv_step = [&](int s2, auto C0) {
-                    const float sc = (lr == s2) ? dinv : 1.0f;
-#pragma unroll
-                    for (int c = decltype(C0)::value; c < 32; ++c) X[c] *= sc;
-                    const float w = x[s2];
-                    if (lr < s2) {
-                        float pv[32];
-#pragma unroll
-                        for (int c = decltype(C0)::value; c < 32; ++c) pv[c] = rl(X[c], s2);
-                        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                        for (int c = decltype(C0)::value; c < 32; ++c) X[c] = fmaf(-w, pv[c], X[c]);
-                    }
-                };
-#pragma unroll 1
-                for (int s2 = 31; s2 >= 24; --s2) uinv_step(s2, std::integral_constant<int, 24>());
-#pragma unroll 1
-                for (int s2 = 23; s2 >= 16; --s2) uinv_step(s2, std::integral_constant<int, 16>());
-#pragma unroll 1
-                for (int s2 = 15; s2 >= 8; --s2) uinv_step(s2, std::integral_constant<int, 8>());
-#pragma unroll 1
-                for (int s2 = 7; s2 >= 0; --s2) uinv_step(s2, std::integral_constant<int, 0>());
-                if (lh == 0) {
-#pragma unroll
-                    for (int c = 0; c < 32; ++c) sUinv[c * TP + lr] = X[c];
-                }
-                // row-major copy, read back transposed so that the global stores coalesce
+                for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = -x[q];
 #pragma unroll
                 for (int q = 0; q < 16; ++q) {
                     const int r = 2 * q + lh;
-                    U64[64 * (o + r) + o + lr] = sUinv[lr * TP + r];
-                    if (o == 32) U64[64 * (32 + r) + lr] = 0.0f;
+                    U64[64 * r + 32 + lr] = sA[lr * TP + r];
                 }
             }
+            return;
         }
-        if (t > 0) {
-            // update t-1 of every trailing tile except (t,t), two tiles per
-            // claim with all their global loads in flight at once
-            const int w = P - t, ntask = w * w - 1;
-            float v[2][16], a[2][16], cv[2][16];
-            for (;;) {
-                const int u = 2 * claim(0);
-                if (u >= ntask) break;
-                const int nt = (u + 1 < ntask) ? 2 : 1;
+        const int t = (ph - 1) / 2;
+        if ((ph - 1) % 2 == 0) {
+            // L(t): update t-1 of trailing tile (i,j) != (t,t)
+            const int w = P - t;
+            const int i = t + (u + 1) % w, j = t + (u + 1) / w;
+            const float* Ug = Tt(t - 1, j);
+            const float* Lg = Tt(i, t - 1);
+            float* Cg = Tt(i, j);
+            // every global load of the task in flight at once
+            float v[16], a[16], cv[16];
 #pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    if (e < nt) {
-                        const int i = t + (u + e + 1) % w, j = t + (u + e + 1) / w;
-                        const float* Ug = Tt(t - 1, j);
-                        const float* Lg = Tt(i, t - 1);
-                        float* Cg = Tt(i, j);
+            for (int q = 0; q < 16; ++q) v[q] = gld(Ug + (int64_t)(2 * q) * ldt + offA);
 #pragma unroll
-                        for (int q = 0; q < 16; ++q) v[e][q] = Ug[(int64_t)(2 * q) * ldt + offA];
+            for (int q = 0; q < 16; ++q) a[q] = gld(Lg + (int64_t)(2 * q) * ldt + offA);
 #pragma unroll
-                        for (int q = 0; q < 16; ++q) a[e][q] = Lg[(int64_t)(2 * q) * ldt + offA];
+            for (int q = 0; q < 16; ++q) cv[q] = gld(Cp(Cg, q));
 #pragma unroll
-                        for (int q = 0; q < 16; ++q) cv[e][q] = Cp(Cg, q);
-                    }
-                }
+            for (int q = 0; q < 16; ++q) sA[(2 * q + lh) * TP + lr] = v[q];
+            const f16v_t acc = prod32([&](int k2) { return a[k2]; }, sQ(sA));
 #pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                    if (e < nt) {
-                        const int i = t + (u + e + 1) % w, j = t + (u + e + 1) / w;
-                        float* Cg = Tt(i, j);
-                        float* S = e ? sB : sA;
-#pragma unroll
-                        for (int q = 0; q < 16; ++q) S[(2 * q + lh) * TP + lr] = v[e][q];
-                        const f16v_t acc = prod32([&](int k2) { return a[e][k2]; }, sQ(S));
-#pragma unroll
-                        for (int q = 0; q < 16; ++q) Cp(Cg, q) = cv[e][q] - acc[q];
-                    }
-                }
-            }
+            for (int q = 0; q < 16; ++q) gst(Cp(Cg, q), cv[q] - acc[q]);
+            return;
         }
-        __syncthreads();
-        if (tid == 0) s_cnt[0] = 0;
-        // ================= phase T(t)
-        {
-            const int w = P - 1 - t;
-            for (;;) {
-                const int u = claim(1);
-                if (u >= 2 * w) break;
-                if (u < w) {
-                    // tile (i,t) <- tile (i,t) U_tt^-1
-                    float* Xg = Tt(t + 1 + u, t);
-                    const f16v_t acc = prod32(gP(Xg), sQ(sUinv));
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        Cp(Xg, q) = acc[q];
-                        sB[res_col(q, lh) * TP + lr] = acc[q];
-                    }
-                    store_final(t + 1 + u, t, sB);
-                } else {
-                    // tile (t,j) <- L_tt^-1 tile (t,j)
-                    float* Yg = Tt(t, t + 1 + (u - w));
-                    stage_cm(sA, Yg, ldt);
-                    const f16v_t acc = prod32(sP(sLinv), sQ(sA));
-#pragma unroll
-                    for (int q = 0; q < 16; ++q) {
-                        Cp(Yg, q) = acc[q];
-                        sB[res_col(q, lh) * TP + lr] = acc[q];
-                    }
-                    store_final(t, t + 1 + (u - w), sB);
-                }
-            }
-        }
-        __syncthreads();
-        if (tid == 0) s_cnt[1] = 0;
-    }
-
-    // ---- off-diagonal blocks of the 64 x 64 inverses
-    for (int u = wave; u < P; u += DW) {
-        if (u < P / 2) {
-            // [L11 0; L21 L22]^-1 = [L11^-1 0; -L22^-1 L21 L11^-1  L22^-1]
-            const int b = u;
-            float* L64 = linv + b * 4096;
-            const float* L21 = Tt(2 * b + 1, 2 * b);
-            stage_cm(sA, L64, 64);
-            const f16v_t y = prod32(gP(L21), sQ(sA));
-#pragma unroll
-            for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = y[q];
-            const float* L22i = L64 + 32 + 64 * 32;
-            const f16v_t x = prod32([=](int k2) { return L22i[128 * k2 + lr + 64 * lh]; }, sQ(sA));
-#pragma unroll
-            for (int q = 0; q < 16; ++q) L64[(32 + lr) + 64 * res_col(q, lh)] = -x[q];
-        } else {
-            // [U11 U12; 0 U22]^-1 = [U11^-1  -U11^-1 U12 U22^-1; 0 U22^-1]
-            const int b = u - P / 2;
-            float* U64 = uinv + b * 4096;
-            const float* U12 = Tt(2 * b, 2 * b + 1);
-            const float* U22i = U64 + 64 * 32 + 32;
-            const f16v_t z = prod32(gP(U12), [=](int k2) { return U22i[128 * k2 + 64 * lh + lr]; });
-#pragma unroll
-            for (int q = 0; q < 16; ++q) sB[res_col(q, lh) * TP + lr] = z[q];
-            stage_rm(sA, U64, 64);
-            const f16v_t x = prod32(sP(sA), sQ(sB));
-#pragma unroll
-            for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = -x[q];
+        // T(t)
+        const int w = P - 1 - t;
+        const int o = 32 * (t & 1);
+        const float* L64 = linv + (t >> 1) * 4096;
+        const float* U64 = uinv + (t >> 1) * 4096;
+        if (u < w) {
+            // tile (i,t) <- tile (i,t) U_tt^-1  (U_tt^-1 from the row-major 64 x 64 block)
+            float* Xg = Tt(t + 1 + u, t);
+            const float* Ui = U64 + 64 * o + o;
+            const f16v_t acc = prod32(gP(Xg), [=](int k2) { return gld(Ui + 64 * (2 * k2 + lh) + lr); });
 #pragma unroll
             for (int q = 0; q < 16; ++q) {
-                const int r = 2 * q + lh;
-                U64[64 * r + 32 + lr] = sA[lr * TP + r];
+                gst(Cp(Xg, q), acc[q]);
+                sB[res_col(q, lh) * TP + lr] = acc[q];
             }
+            store_final(t + 1 + u, t, sB);
+        } else {
+            // tile (t,j) <- L_tt^-1 tile (t,j)  (L_tt^-1 from the column-major 64 x 64 block)
+            float* Yg = Tt(t, t + 1 + (u - w));
+            const float* Li = L64 + o + 64 * o;
+            stage_cm(sA, Yg, ldt);
+            const f16v_t acc = prod32([=](int k2) { return gld(Li + lr + 64 * (2 * k2 + lh)); }, sQ(sA));
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                gst(Cp(Yg, q), acc[q]);
+                sB[res_col(q, lh) * TP + lr] = acc[q];
+            }
+            store_final(t, t + 1 + (u - w), sB);
+        }
+    };
+
+    // every wave: from the open phase on, take part in each phase in turn
+    int ph = ild(phase);
+    for (; ph < NP; ++ph) {
+        if (phase_target(ph, P) == 0) continue;
+        if (!wait_phase(ph)) return;
+        const bool lphase = ph >= 1 && ph <= 2 * P && (ph - 1) % 2 == 0;
+        if (leader && lphase) {
+            leaf((ph - 1) / 2);
+            complete(ph);
+        }
+        const int nclaim = phase_claims(ph, P);
+        for (;;) {
+            const int u = claim(ph);
+            if (u >= nclaim) break;
+            task(ph, u);
+            complete(ph);
         }
     }
 }
 
-size_t diag_lu_smem() { return (size_t)(2 * DW + 2) * TILE_F * sizeof(float); }
+size_t diag_lu_smem() { return (size_t)(2 * DW) * TILE_F * sizeof(float); }
+size_t diag_sync_words() { return 1 + 2 * NPMAX; }
 
 template <int ST>
 static hipError_t diag_lu_typed(void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
-                                float* linv, float* uinv, unsigned long long* info, hipStream_t s) {
+                                float* linv, float* uinv, int* sync, unsigned long long* info, hipStream_t s) {
     static const hipError_t attr = hipFuncSetAttribute((const void*)k_diag_lu<ST>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_lu_smem());
     if (attr) return attr;
-    k_diag_lu<ST><<<1, DT, diag_lu_smem(), s>>>((typename Store<ST>::T*)A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv,
-                                                info);
+    // helpers scale with the work (a 512 block: one leader and three helpers)
+    const int P = kbp / 32;
+    int wgs = P / 4;
+    wgs = wgs < 1 ? 1 : (wgs > 8 ? 8 : wgs);
+    k_diag_lu<ST><<<wgs, DT, diag_lu_smem(), s>>>((typename Store<ST>::T*)A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv,
+                                                 sync, info);
     return hipGetLastError();
 }
 
 hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
-                   float* linv, float* uinv, unsigned long long* info, hipStream_t s) {
-    if (kb < 1 || kbp % 64 || kbp > ldt || kb > kbp) return hipErrorInvalidValue;
+                   float* linv, float* uinv, int* sync, unsigned long long* info, hipStream_t s) {
+    if (kb < 1 || kbp % 64 || kbp > ldt || kb > kbp || kbp > 1024) return hipErrorInvalidValue;
     switch (store) {
-    case F32: return diag_lu_typed<F32>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, info, s);
-    case F16: return diag_lu_typed<F16>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, info, s);
-    case BF16: return diag_lu_typed<BF16>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, info, s);
+    case F32: return diag_lu_typed<F32>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, sync, info, s);
+    case F16: return diag_lu_typed<F16>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, sync, info, s);
+    case BF16: return diag_lu_typed<BF16>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, sync, info, s);
     default: return hipErrorInvalidValue;
     }
 }

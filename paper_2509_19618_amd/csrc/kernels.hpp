@@ -38,13 +38,14 @@ struct FactorPlan {
     float* inv_sa;   // 2 sets of op_rows/32
     float* inv_sb;   // 2 sets of op_rows/32
     unsigned long long* info;  // 1
+    int* dsync;      // nblk x diag_sync_words(): phase counters of the diagonal-block LUs (zeroed per factorisation)
 };
 
 struct AuxLayout {
     size_t T, Trm, linv, uinv, lsc, rowscale, linv_full, uinv_full, total;
 };
 struct WorkLayout {
-    size_t Lq, Uq, inv_sa, inv_sb, info, total;
+    size_t Lq, Uq, inv_sa, inv_sb, info, dsync, total;
 };
 AuxLayout aux_layout(int64_t n, int64_t nb);
 int64_t operand_rows(int64_t n);
@@ -55,10 +56,14 @@ int dtype_bytes(int dt);
 hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq,
                        const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s);
 // FP32 LU of the diagonal block A[k:k+kb, k:k+kb] (padded to kbp, a multiple
-// of 64, with the identity) in one work-group: T/Trm (ld ldt) get L\U column-
-// and row-major, linv/uinv the 64x64 sub-block inverses, A the factored block.
+// of 64, with the identity) by a few cooperating work-groups: T/Trm (ld ldt)
+// get L\U column- and row-major, linv/uinv the 64x64 sub-block inverses, A
+// the factored block.  sync: diag_sync_words() zeroed ints for this call.  A
+// zero / non-finite pivot sets *info (atomic min) to its 1-based column; an
+// expired wait sets it to 2^62.
+size_t diag_sync_words();
 hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
-                   float* linv, float* uinv, unsigned long long* info, hipStream_t s);
+                   float* linv, float* uinv, int* sync, unsigned long long* info, hipStream_t s);
 hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t s);
 // Side stream and events of the look-ahead (default stream priority).  A
 // factorisation uses the caller's context, or a per-device one if la is NULL;

@@ -64,6 +64,7 @@ WorkLayout work_layout(int64_t n, int64_t nb, int update) {
     W.inv_sa = off; off = al256(off + 2 * (size_t)(rows / 32) * 4);
     W.inv_sb = off; off = al256(off + 2 * (size_t)(rows / 32) * 4);
     W.info = off; off = al256(off + 8);
+    W.dsync = off; off = al256(off + (size_t)((n + nb - 1) / nb) * diag_sync_words() * 4);
     W.total = off;
     return W;
 }
@@ -443,7 +444,8 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         float* linv = p.linv + blk * nb * 64;
         float* uinv = p.uinv + blk * nb * 64;
         hipEvent_t pt = prof::begin(st);
-        hipError_t e2 = diag_lu(ST, A, lda, k, kb, kbp, T, p.Trm + blk * nb * nb, nb, linv, uinv, p.info, st);
+        hipError_t e2 = diag_lu(ST, A, lda, k, kb, kbp, T, p.Trm + blk * nb * nb, nb, linv, uinv,
+                                p.dsync + blk * diag_sync_words(), p.info, st);
         if (e2) return e2;
         prof::end(pt, prof::DIAG, st, 2.0 / 3.0 * kb * (double)kb * kb, 2.0 * kb * (double)kb * sizeof(ST_T));
         return hipGetLastError();
@@ -492,6 +494,10 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     };
 
     if ((e = fill_u64(p.info, 1, ~0ull, s))) return e;
+    {
+        const int64_t words = ((n + nb - 1) / nb) * (int64_t)diag_sync_words();
+        if ((e = fill_u64(p.dsync, (words + 1) / 2, 0ull, s))) return e;
+    }
     if ((e = diag(0, s))) return e;
     if ((e = trsm(0, s))) return e;
     for (int64_t k = 0; k + nb < n; k += nb) {
