@@ -479,9 +479,9 @@ static hipError_t diag_lu_typed(void* A, int64_t lda, int64_t k, int kb, int kbp
     static const hipError_t attr = hipFuncSetAttribute((const void*)k_diag_lu<ST>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_lu_smem());
     if (attr) return attr;
-    // helpers scale with the work (a 512 block: one leader and three helpers)
+    // helpers scale with the work (a 512 block: one leader and seven helpers)
     const int P = kbp / 32;
-    int wgs = P / 4;
+    int wgs = P / 2;
     wgs = wgs < 1 ? 1 : (wgs > 8 ? 8 : wgs);
     k_diag_lu<ST><<<wgs, DT, diag_lu_smem(), s>>>((typename Store<ST>::T*)A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv,
                                                  sync, info);
