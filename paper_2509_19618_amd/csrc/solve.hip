@@ -105,20 +105,40 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
     if (tid < TS) w[tid] = (tid < rows) ? rhs[r0 + tid] : 0.0;
     const bool vload = vec && rows == TS;
     const int rg = lane % RG, cl = lane / RG;
+    constexpr int PF = 16;                     // panel loads issued before the dependency's flag is awaited
     for (int64_t i = LOWER ? 0 : J - 1; i != j; i += LOWER ? 1 : -1) {
-        if (!wait_flag(&ready[i], strips_of(i), err, &s_abort)) return;
         const int64_t c0 = i * nb;
         const int kbi = (int)(n - c0 < nb ? n - c0 : nb);
+        const int q = (kbi + 3) / 4, cb = wv * q, ce = (cb + q < kbi) ? cb + q : kbi;
+        const T* base = A + r0 + RPL * rg + c0 * lda;
+        // the factor panel does not depend on the flag: its loads overlap the wait
+        uint4 pre[PF];
+        if (vload) {
+#pragma unroll
+            for (int m = 0; m < PF; ++m) {
+                const int c = cb + cl + m * CPI;
+                if (c < ce) pre[m] = *(const uint4*)(base + (int64_t)c * lda);
+            }
+        }
+        if (!wait_flag(&ready[i], strips_of(i), err, &s_abort)) return;
         for (int c = tid; c < kbi; c += 256) zs[c] = get_shared(out + c0 + c);
         __syncthreads();
         double acc[RPL];
 #pragma unroll
         for (int k = 0; k < RPL; ++k) acc[k] = 0.0;
-        const int q = (kbi + 3) / 4, cb = wv * q, ce = (cb + q < kbi) ? cb + q : kbi;
-        const T* base = A + r0 + RPL * rg + c0 * lda;
         if (vload) {
+#pragma unroll
+            for (int m = 0; m < PF; ++m) {
+                const int c = cb + cl + m * CPI;
+                if (c < ce) {
+                    const T* e = (const T*)&pre[m];
+                    const double zc = zs[c];
+#pragma unroll
+                    for (int k = 0; k < RPL; ++k) acc[k] += (double)Store<ST>::load(e, k) * zc;
+                }
+            }
 #pragma unroll 4
-            for (int c = cb + cl; c < ce; c += CPI) {
+            for (int c = cb + cl + PF * CPI; c < ce; c += CPI) {
                 const uint4 v = *(const uint4*)(base + (int64_t)c * lda);
                 const T* e = (const T*)&v;
                 const double zc = zs[c];
