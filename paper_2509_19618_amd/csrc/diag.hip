@@ -7,15 +7,21 @@
 // dependent steps over 32 x 32 tiles of an FP32 copy T (column-major, ld =
 // ldt), right-looking:
 //
-//   phase load:  T <- A11 (tile tasks)
 //   for t = 0 .. P-1   (P = kbp / 32)
-//     phase L(t): the leader (waves 0 and 1 of work-group 0) applies the last
+//     phase L(t): the leader (wave 0 of work-group 0) applies the last
 //                 update to tile (t,t) and factors it in registers (row r of
-//                 the tile in lane r), then wave 0 forms the inverse of the
-//                 unit-lower factor and wave 1 that of the upper one; every
-//                 other wave applies update t-1 to the other trailing tiles;
-//     phase T(t): tiles (i,t) <- tile(i,t) U_tt^-1, (t,j) <- L_tt^-1 tile(t,j)
+//                 the tile in lane r); every other wave applies update t-1
+//                 to the other trailing tiles;
+//     phase T(t): tiles (i,t) <- tile(i,t) U_tt^-1 and (t,j) <- L_tt^-1 tile(t,j),
+//                 each by substitution against the factored tile (t,t)
+//   (the first access to a tile reads it from A; T holds it from then on)
+//   phase inv:   the inverses of the 32 x 32 unit-lower and upper diagonal
+//                tiles (one wave each, all at once);
 //   phase asm:   off-diagonal blocks of the 64 x 64 sub-block inverses.
+//
+// The chain of dependent steps is the leaf factorisations and the
+// substitutions; the tile inverses, needed only by the strip TRSMs that
+// follow, stay off it.
 //
 // One launch of a few work-groups of four waves (each fits on a CU beside a
 // work-group of the concurrent trailing update).  Every wave works on its
@@ -24,12 +30,14 @@
 // Work-groups that start late simply join the current phase, so the leader
 // never waits for a helper to be scheduled.  T and the tile inverses are
 // read and written with device-scope accesses (they go to the device's
-// coherence point), a wave's stores are acknowledged before it counts a task
-// done, and every wait is bounded: on expiry it records an error in *info
+// coherence point), a wave's stores to T are acknowledged before it counts a
+// task done (the final copies to A and Trm, read only after the launch, are
+// written after that), and every wait is bounded: on expiry it records an error in *info
 // and the wave exits.
 //
 // Every 32 x 32 x 32 product is one wave's chain of sixteen
-// v_mfma_f32_32x32x2f32.  The kernel also writes the inverses of the 64 x 64
+// v_mfma_f32_32x32x2f32; a substitution is one wave's chain of FMAs with
+// the triangular factor read from LDS four entries at a time.  The kernel also writes the inverses of the 64 x 64
 // unit-lower (column-major) and upper (row-major) diagonal sub-blocks used by
 // the strip TRSMs, the factored block back into A in the storage format, and
 // a row-major copy Trm of T.
@@ -51,7 +59,8 @@ typedef float v32f __attribute__((ext_vector_type(32)));
 constexpr int DW = 4;              // waves of the work-group
 constexpr int DT = DW * 64;        // threads
 constexpr int TP = 33;             // LDS pitch of a staged 32 x 32 tile (column-major)
-constexpr int TILE_F = 32 * TP;    // floats of one staged tile
+constexpr int SP = 36;             // LDS pitch of a staged triangular factor (16-byte rows)
+constexpr int TILE_F = 32 * SP;    // floats of one staging buffer
 
 // v, hidden from the optimiser (keeps loop-invariant per-lane constants
 // from being hoisted out of the block loop and held in registers throughout)
@@ -59,6 +68,15 @@ MXP_DEV int opaque(int v) {
     asm volatile("" : "+v"(v));
     return v;
 }
+
+// LDS accesses of one wave execute in order; this keeps the compiler from
+// moving them across each other (reads through float4 and writes through
+// float do not alias by type)
+MXP_DEV void lds_order() { asm volatile("" ::: "memory"); }
+
+// v, computed before this point in program order (the instruction selector
+// otherwise sinks arithmetic of an unrolled chain away from its loads)
+MXP_DEV void pin(float& v) { asm volatile("" : "+v"(v)); }
 
 MXP_DEV float rl(float v, int l) { return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l)); }
 
@@ -68,8 +86,7 @@ MXP_DEV void gst(float* p, float v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED,
 MXP_DEV int ild(const int* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 // s[c*TP + r] = g[r + c*ld] for r, c < 32 (lanes along r: coalesced)
-MXP_DEV void stage_cm(float* s, const float* g, int64_t ld) {
-    const int lane = threadIdx.x & 63, r = lane & 31, h = lane >> 5;
+MXP_DEV void stage_cm(float* s, const float* g, int64_t ld, int r, int h) {
     float v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = gld(g + (int64_t)(2 * q) * ld + (r + h * (int)ld));
@@ -78,8 +95,7 @@ MXP_DEV void stage_cm(float* s, const float* g, int64_t ld) {
 }
 
 // s[c*TP + r] = g[r*ld + c] for r, c < 32 (lanes along c: coalesced)
-MXP_DEV void stage_rm(float* s, const float* g, int64_t ld) {
-    const int lane = threadIdx.x & 63, c = lane & 31, h = lane >> 5;
+MXP_DEV void stage_rm(float* s, const float* g, int64_t ld, int c, int h) {
     float v[16];
 #pragma unroll
     for (int q = 0; q < 16; ++q) v[q] = gld(g + (int64_t)(2 * q) * ld + (c + h * (int)ld));
@@ -112,20 +128,19 @@ MXP_DEV int res_col(int q, int lh) { return 8 * (q >> 2) + 4 * lh + (q & 3); }
 // uniform part of res_col
 MXP_DEV int res_colu(int q) { return 8 * (q >> 2) + (q & 3); }
 
-// phases of one diagonal-block LU and their sizes (see the file comment)
+// phases of one diagonal-block LU and their sizes (see the file comment):
+// 2t L(t), 2t + 1 T(t), 2P inv, 2P + 1 asm
 constexpr int NPMAX = 2 * 32 + 2;   // phases for kbp <= 1024
 MXP_DEV int phase_claims(int ph, int P) {
-    if (ph == 0) return P * P;                         // load
+    if (ph == 2 * P) return 2 * P;                     // tile inverses
     if (ph == 2 * P + 1) return P;                     // inverse assembly
-    const int t = (ph - 1) / 2;
-    if ((ph - 1) % 2 == 0) return t > 0 ? (P - t) * (P - t) - 1 : 0;   // L(t): updates of step t-1
+    const int t = ph / 2;
+    if (ph % 2 == 0) return t > 0 ? (P - t) * (P - t) - 1 : 0;   // L(t): updates of step t-1
     return 2 * (P - 1 - t);                            // T(t)
 }
-// completions that close a phase: its claims, plus the two leaf waves in L(t)
-MXP_DEV int phase_target(int ph, int P) {
-    const bool lphase = ph >= 1 && ph <= 2 * P && (ph - 1) % 2 == 0;
-    return phase_claims(ph, P) + (lphase ? 2 : 0);
-}
+MXP_DEV bool is_lphase(int ph, int P) { return ph < 2 * P && ph % 2 == 0; }
+// completions that close a phase: its claims, plus the leaf in L(t)
+MXP_DEV int phase_target(int ph, int P) { return phase_claims(ph, P) + (is_lphase(ph, P) ? 1 : 0); }
 
 }  // namespace
 
@@ -136,7 +151,9 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
                                                 unsigned long long* info) {
     extern __shared__ __attribute__((aligned(16))) float dsm[];
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int lr = lane & 31, lh = lane >> 5;
+    // lane-derived values, remade through opaque() before every task (see
+    // refresh below)
+    int lr = lane & 31, lh = lane >> 5;
     float* sA = dsm + (2 * wave) * TILE_F;       // two staging tiles per wave
     float* sB = sA + TILE_F;
     const int P = kbp / 32;
@@ -144,10 +161,19 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
     int* phase = sync;                           // the open phase (NP = finished)
     int* claims = sync + 1;
     int* dones = sync + 1 + NPMAX;
-    const bool leader = blockIdx.x == 0 && wave < 2;
+    const bool leader = blockIdx.x == 0 && wave == 0;
     auto Tt = [&](int I, int J) -> float* { return T + 32 * I + (int64_t)(32 * J) * ldt; };
-    const int offA = lr + lh * ldt;          // lane offset of operand element (lr, 2 k2 + lh) of a T tile
-    const int offC = lr + 4 * lh * ldt;      // lane offset of result element (lr, res_col(q))
+    int offA = lr + lh * ldt;                // lane offset of operand element (lr, 2 k2 + lh) of a T tile
+    int offC = lr + 4 * lh * ldt;            // lane offset of result element (lr, res_col(q))
+    // every task and leaf starts from fresh lane values: addresses derived
+    // from them then cannot be hoisted out of the phase loop, where the
+    // invariants of all task kinds would stay live at once
+    auto refresh = [&]() {
+        lr = opaque(lane & 31);
+        lh = opaque(lane >> 5);
+        offA = lr + lh * (int)ldt;
+        offC = lr + 4 * lh * (int)ldt;
+    };
     // operand fetchers: P[lr][k] of a T tile, P and Q of a staged LDS tile
     auto gP = [&](const float* G) { return [=](int k2) { return gld(G + (int64_t)(2 * k2) * ldt + offA); }; };
     auto sQ = [&](const float* S) { return [=](int k2) { return S[lr * TP + 2 * k2 + lh]; }; };
@@ -163,6 +189,14 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
             if (i < kb && j < kb) A[(k + i) + (k + j) * lda] = Store<ST>::from_f32(S[(2 * q + lh) * TP + lr]);
             Trm[(32 * J + lr) + (int64_t)(32 * I + 2 * q + lh) * ldt] = S[lr * TP + 2 * q + lh];
         }
+    };
+    // element (i,j) of the diagonal block in FP32 from A, padded with the
+    // identity beyond kb (the first access to a tile; plain loads: A is not
+    // written before that)
+    auto a_el = [&](int i, int j) -> float {
+        const bool in = i < kb && j < kb;
+        const float v = Store<ST>::load(A, in ? (k + i) + (k + j) * lda : k + k * lda);
+        return in ? v : ((i == j) ? 1.0f : 0.0f);
     };
     auto fail = [&]() {
         if (lane == 0) atomicMin(info, 1ull << 62);
@@ -188,7 +222,7 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
         old = __builtin_amdgcn_readfirstlane(old);
         if (old + 1 == phase_target(ph, P)) {
             // T(P-1) is the only empty phase
-            const int nx = (ph + 1 == 2 * P) ? ph + 2 : ph + 1;
+            const int nx = (ph + 1 == 2 * P - 1) ? ph + 2 : ph + 1;
             if (lane == 0) __hip_atomic_store(phase, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     };
@@ -198,18 +232,34 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
         return __builtin_amdgcn_readfirstlane(v);
     };
 
-    // the leaf of step t (leader waves only)
-    auto leaf = [&](int t) {
+    // the leaf of step t (the leader wave only), phase ph = L(t)
+    auto leaf = [&](int t, int ph) {
         // tile (t,t) after the last update, into sA (column-major, pitch TP)
         if (t == 0) {
-            stage_cm(sA, Tt(0, 0), ldt);
-        } else {
-            stage_cm(sB, Tt(t - 1, t), ldt);
-            const float* Lg = Tt(t, t - 1);
-            const f16v_t acc = prod32(gP(Lg), sQ(sB));
-            float* Cg = Tt(t, t);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = gld(Cp(Cg, q)) - acc[q];
+            for (int q = 0; q < 16; ++q) sA[(2 * q + lh) * TP + lr] = a_el(lr, 2 * q + lh);
+        } else {
+            // every load of the update in flight at once
+            const float* Ug = Tt(t - 1, t);
+            const float* Lg = Tt(t, t - 1);
+            float* Cg = Tt(t, t);
+            float v[16], a[16], cv[16];
+#pragma unroll
+            for (int q = 0; q < 16; ++q) v[q] = gld(Ug + (int64_t)(2 * q) * ldt + offA);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) a[q] = gld(Lg + (int64_t)(2 * q) * ldt + offA);
+            if (t == 1) {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) cv[q] = a_el(32 + lr, 32 + res_col(q, lh));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) cv[q] = gld(Cp(Cg, q));
+            }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sB[(2 * q + lh) * TP + lr] = v[q];
+            const f16v_t acc = prod32([&](int k2) { return a[k2]; }, sQ(sB));
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = cv[q] - acc[q];
         }
         // LU in registers: lane r (and r + 32) holds row r.  The step loop
         // stays rolled (small code: the kernel runs once per block, its
@@ -221,12 +271,10 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
         v32f x;
 #pragma unroll
         for (int c = 0; c < 32; ++c) x[c] = sA[c * TP + lr];
-        float dinv = 0.0f;   // lane j: 1 / U[j][j]
         auto lu_step = [&](int j, auto C0) {
             const int lr = opaque(lane & 31);
             const float xj = x[j];
             const float rp = __builtin_amdgcn_rcpf(rl(xj, j));   // v_rcp_f32 (1 ulp)
-            dinv = (lr == j) ? rp : dinv;
             if (lr > j) {
                 // rows at or above the pivot stay as they are (readlane
                 // reads the pivot lane whatever the execution mask)
@@ -244,121 +292,135 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
         for (int j = 16; j < 24; ++j) lu_step(j, std::integral_constant<int, 16>());
 #pragma unroll 1
         for (int j = 24; j < 31; ++j) lu_step(j, std::integral_constant<int, 24>());
-        dinv = (lr == 31) ? __builtin_amdgcn_rcpf(rl(x[31], 31)) : dinv;
-        const int o = 32 * (t & 1);
-        float* L64 = linv + (t >> 1) * 4096;   // column-major 64 x 64
-        float* U64 = uinv + (t >> 1) * 4096;   // row-major 64 x 64
+        float* Cg = Tt(t, t);
+        if (lh == 0) {
+#pragma unroll
+            for (int c = 0; c < 32; ++c) {
+                const float f = (c >= lr) ? x[c] : sA[c * TP + lr];
+                gst(Cg + lr + (int64_t)c * ldt, f);
+                sB[c * TP + lr] = f;
+            }
+        }
+        complete(ph);
+        store_final(t, t, sB);
+        // the pivots are the diagonal of U: report the first zero / non-finite one
+        int bad = -1;
+#pragma unroll
+        for (int c = 31; c >= 0; --c) {
+            const float d = rl(x[c], c);
+            if (32 * t + c < kb && !(d != 0.0f && isfinite(d))) bad = c;
+        }
+        if (bad >= 0 && lane == 0) atomicMin(info, (unsigned long long)(k + 32 * t + bad + 1));
+    };
+
+    // the inverse of the unit-lower factor of tile (t,t), as block (t&1, t&1)
+    // of the column-major 64 x 64 inverse t/2 (zero above the diagonal)
+    auto tile_linv = [&](int t) {
+        stage_cm(sA, Tt(t, t), ldt, lr, lh);
+        lds_order();
         float X[32];
         const int lro = opaque(lr);
 #pragma unroll
         for (int c = 0; c < 32; ++c) X[c] = (c == lro) ? 1.0f : 0.0f;
-        if (wave == 0) {
-            float* Cg = Tt(t, t);
-            if (lh == 0) {
+        // by rows: X[i] = e_i - sum_{s<i} L[i][s] X[s]; row s of X is zero
+        // right of s, so the sweep stops at C1
+        auto linv_step = [&](int s2, auto C1) {
+            constexpr int c1 = decltype(C1)::value;
+            const int lr = opaque(lane & 31);
+            if (lr > s2) {
+                const float l = sA[s2 * TP + lr];
+                // all broadcasts first (kept apart from the FMAs so that
+                // the readlane results pipeline instead of alternating)
+                float pv[c1];
 #pragma unroll
-                for (int c = 0; c < 32; ++c) {
-                    const float f = (c >= lr) ? x[c] : sA[c * TP + lr];
-                    gst(Cg + lr + (int64_t)c * ldt, f);
-                    sB[c * TP + lr] = f;
-                }
+                for (int c = 0; c < c1; ++c) pv[c] = rl(X[c], s2);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = 0; c < c1; ++c) X[c] = fmaf(-l, pv[c], X[c]);
             }
-            store_final(t, t, sB);
-            // the pivots are the diagonal of U: report the first zero / non-finite one
-            int bad = -1;
-#pragma unroll
-            for (int c = 31; c >= 0; --c) {
-                const float d = rl(x[c], c);
-                if (32 * t + c < kb && !(d != 0.0f && isfinite(d))) bad = c;
-            }
-            if (bad >= 0 && lane == 0) atomicMin(info, (unsigned long long)(k + 32 * t + bad + 1));
-            // L^-1 by rows: X[i] = e_i - sum_{s<i} L[i][s] X[s]
-            // (row s of X is zero right of s: the sweep stops at C1)
-            auto linv_step = [&](int s2, auto C1) {
-                constexpr int c1 = decltype(C1)::value;
-                const int lr = opaque(lane & 31);
-                if (lr > s2) {
-                    const float l = sA[s2 * TP + lr];
-                    // all broadcasts first (kept apart from the FMAs so that
-                    // the readlane results pipeline instead of alternating)
-                    float pv[c1];
-#pragma unroll
-                    for (int c = 0; c < c1; ++c) pv[c] = rl(X[c], s2);
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int c = 0; c < c1; ++c) X[c] = fmaf(-l, pv[c], X[c]);
-                }
-            };
+        };
 #pragma unroll 1
-            for (int s2 = 0; s2 < 8; ++s2) linv_step(s2, std::integral_constant<int, 8>());
+        for (int s2 = 0; s2 < 8; ++s2) linv_step(s2, std::integral_constant<int, 8>());
 #pragma unroll 1
-            for (int s2 = 8; s2 < 16; ++s2) linv_step(s2, std::integral_constant<int, 16>());
+        for (int s2 = 8; s2 < 16; ++s2) linv_step(s2, std::integral_constant<int, 16>());
 #pragma unroll 1
-            for (int s2 = 16; s2 < 24; ++s2) linv_step(s2, std::integral_constant<int, 24>());
+        for (int s2 = 16; s2 < 24; ++s2) linv_step(s2, std::integral_constant<int, 24>());
 #pragma unroll 1
-            for (int s2 = 24; s2 < 31; ++s2) linv_step(s2, std::integral_constant<int, 32>());
-            if (lh == 0) {
+        for (int s2 = 24; s2 < 31; ++s2) linv_step(s2, std::integral_constant<int, 32>());
+        const int o = 32 * (t & 1);
+        float* L64 = linv + (t >> 1) * 4096;
+        if (lh == 0) {
 #pragma unroll
-                for (int c = 0; c < 32; ++c) {
-                    gst(L64 + (o + lr) + 64 * (o + c), X[c]);
-                    if (o == 0) gst(L64 + lr + 64 * (32 + c), 0.0f);
-                }
-            }
-        } else {
-            // U^-1 by rows, last row first: X[i] = (e_i - sum_{s>i} U[i][s] X[s]) / U[i][i]
-            // (row s of X is zero left of s: the sweep starts at C0)
-            auto uinv_step = [&](int s2, auto C0) {
-                const int lr = opaque(lane & 31);
-                const float sc = (lr == s2) ? dinv : 1.0f;
-#pragma unroll
-                for (int c = decltype(C0)::value; c < 32; ++c) X[c] *= sc;
-                const float w = x[s2];
-                if (lr < s2) {
-                    float pv[32];
-#pragma unroll
-                    for (int c = decltype(C0)::value; c < 32; ++c) pv[c] = rl(X[c], s2);
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int c = decltype(C0)::value; c < 32; ++c) X[c] = fmaf(-w, pv[c], X[c]);
-                }
-            };
-#pragma unroll 1
-            for (int s2 = 31; s2 >= 24; --s2) uinv_step(s2, std::integral_constant<int, 24>());
-#pragma unroll 1
-            for (int s2 = 23; s2 >= 16; --s2) uinv_step(s2, std::integral_constant<int, 16>());
-#pragma unroll 1
-            for (int s2 = 15; s2 >= 8; --s2) uinv_step(s2, std::integral_constant<int, 8>());
-#pragma unroll 1
-            for (int s2 = 7; s2 >= 0; --s2) uinv_step(s2, std::integral_constant<int, 0>());
-            if (lh == 0) {
-#pragma unroll
-                for (int c = 0; c < 32; ++c) sA[c * TP + lr] = X[c];
-            }
-            // row-major copy, read back transposed so that the stores coalesce
-#pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int r = 2 * q + lh;
-                gst(U64 + 64 * (o + r) + o + lr, sA[lr * TP + r]);
-                if (o == 32) gst(U64 + 64 * (32 + r) + lr, 0.0f);
+            for (int c = 0; c < 32; ++c) {
+                gst(L64 + (o + lr) + 64 * (o + c), X[c]);
+                if (o == 0) gst(L64 + lr + 64 * (32 + c), 0.0f);
             }
         }
     };
 
-    // one task u of phase ph
-    auto task = [&](int ph, int u) {
-        if (ph == 0) {
-            // load: T tile <- A11 tile in FP32, padded with the identity
-            const int I = u % P, J = u / P;
-            const int i = 32 * I + lr;
-            float v[16];
+    // the inverse of the upper factor of tile (t,t), as block (t&1, t&1) of
+    // the row-major 64 x 64 inverse t/2 (zero below the diagonal)
+    auto tile_uinv = [&](int t) {
+        stage_cm(sA, Tt(t, t), ldt, lr, lh);
+        lds_order();
+        v32f x;   // read at the step index (s_set_gpr_idx)
+        float X[32];
+        const int lro = opaque(lr);
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                const int j = 32 * J + 2 * q + lh;
-                const bool in = i < kb && j < kb;
-                v[q] = Store<ST>::load(A, in ? (k + i) + (k + j) * lda : k + k * lda);
-                v[q] = in ? v[q] : ((i == j) ? 1.0f : 0.0f);
+        for (int c = 0; c < 32; ++c) {
+            x[c] = sA[c * TP + lr];                 // row lr of the tile (U right of the diagonal)
+            X[c] = (c == lro) ? 1.0f : 0.0f;
+        }
+        const float dinv = __builtin_amdgcn_rcpf(sA[lro * TP + lro]);   // 1 / U[lr][lr], as in the leaf
+        // by rows, last row first: X[i] = (e_i - sum_{s>i} U[i][s] X[s]) / U[i][i];
+        // row s of X is zero left of s, so the sweep starts at C0
+        auto uinv_step = [&](int s2, auto C0) {
+            const int lr = opaque(lane & 31);
+            const float sc = (lr == s2) ? dinv : 1.0f;
+#pragma unroll
+            for (int c = decltype(C0)::value; c < 32; ++c) X[c] *= sc;
+            const float w = x[s2];
+            if (lr < s2) {
+                float pv[32];
+#pragma unroll
+                for (int c = decltype(C0)::value; c < 32; ++c) pv[c] = rl(X[c], s2);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int c = decltype(C0)::value; c < 32; ++c) X[c] = fmaf(-w, pv[c], X[c]);
             }
+        };
+#pragma unroll 1
+        for (int s2 = 31; s2 >= 24; --s2) uinv_step(s2, std::integral_constant<int, 24>());
+#pragma unroll 1
+        for (int s2 = 23; s2 >= 16; --s2) uinv_step(s2, std::integral_constant<int, 16>());
+#pragma unroll 1
+        for (int s2 = 15; s2 >= 8; --s2) uinv_step(s2, std::integral_constant<int, 8>());
+#pragma unroll 1
+        for (int s2 = 7; s2 >= 0; --s2) uinv_step(s2, std::integral_constant<int, 0>());
+        lds_order();
+        if (lh == 0) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) gst(T + i + (int64_t)(32 * J + 2 * q + lh) * ldt, v[q]);
+            for (int c = 0; c < 32; ++c) sA[c * TP + lr] = X[c];
+        }
+        lds_order();
+        // row-major copy, read back transposed so that the stores coalesce
+        const int o = 32 * (t & 1);
+        float* U64 = uinv + (t >> 1) * 4096;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int r = 2 * q + lh;
+            gst(U64 + 64 * (o + r) + o + lr, sA[lr * TP + r]);
+            if (o == 32) gst(U64 + 64 * (32 + r) + lr, 0.0f);
+        }
+    };
+
+    // one task u of phase ph; it counts itself done (complete) as soon as its
+    // stores to T are acknowledged
+    auto task = [&](int ph, int u) {
+        if (ph == NP - 2) {
+            if (u < P) tile_linv(u);
+            else tile_uinv(u - P);
+            complete(ph);
             return;
         }
         if (ph == NP - 1) {
@@ -367,7 +429,7 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
                 const int b = u;
                 float* L64 = linv + b * 4096;
                 const float* L21 = Tt(2 * b + 1, 2 * b);
-                stage_cm(sA, L64, 64);
+                stage_cm(sA, L64, 64, lr, lh);
                 const f16v_t y = prod32(gP(L21), sQ(sA));
 #pragma unroll
                 for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = y[q];
@@ -384,7 +446,7 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
                 const f16v_t z = prod32(gP(U12), [=](int k2) { return gld(U22i + 128 * k2 + 64 * lh + lr); });
 #pragma unroll
                 for (int q = 0; q < 16; ++q) sB[res_col(q, lh) * TP + lr] = z[q];
-                stage_rm(sA, U64, 64);
+                stage_rm(sA, U64, 64, lr, lh);
                 const f16v_t x = prod32(sP(sA), sQ(sB));
 #pragma unroll
                 for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = -x[q];
@@ -394,10 +456,11 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
                     U64[64 * r + 32 + lr] = sA[lr * TP + r];
                 }
             }
+            complete(ph);
             return;
         }
-        const int t = (ph - 1) / 2;
-        if ((ph - 1) % 2 == 0) {
+        const int t = ph / 2;
+        if (ph % 2 == 0) {
             // L(t): update t-1 of trailing tile (i,j) != (t,t)
             const int w = P - t;
             const int i = t + (u + 1) % w, j = t + (u + 1) / w;
@@ -410,43 +473,120 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
             for (int q = 0; q < 16; ++q) v[q] = gld(Ug + (int64_t)(2 * q) * ldt + offA);
 #pragma unroll
             for (int q = 0; q < 16; ++q) a[q] = gld(Lg + (int64_t)(2 * q) * ldt + offA);
+            if (t == 1) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) cv[q] = gld(Cp(Cg, q));
+                for (int q = 0; q < 16; ++q) cv[q] = a_el(32 * i + lr, 32 * j + res_col(q, lh));
+            } else {
+#pragma unroll
+                for (int q = 0; q < 16; ++q) cv[q] = gld(Cp(Cg, q));
+            }
 #pragma unroll
             for (int q = 0; q < 16; ++q) sA[(2 * q + lh) * TP + lr] = v[q];
             const f16v_t acc = prod32([&](int k2) { return a[k2]; }, sQ(sA));
 #pragma unroll
             for (int q = 0; q < 16; ++q) gst(Cp(Cg, q), cv[q] - acc[q]);
+            complete(ph);
             return;
         }
-        // T(t)
+        // T(t), by substitution against the factored tile (t,t), staged in
+        // sA with pitch SP so that four consecutive factor entries are one
+        // 16-byte LDS read (the same address in every lane: a broadcast)
         const int w = P - 1 - t;
-        const int o = 32 * (t & 1);
-        const float* L64 = linv + (t >> 1) * 4096;
-        const float* U64 = uinv + (t >> 1) * 4096;
+        const float* Fg = Tt(t, t);
+        const int lo = lr, ho = lh;
+        float b[32];
         if (u < w) {
-            // tile (i,t) <- tile (i,t) U_tt^-1  (U_tt^-1 from the row-major 64 x 64 block)
+            // tile (i,t) <- tile (i,t) U_tt^-1: X U = B row by row, lane r
+            // holding row r; U is staged row-major (sA[s*SP + c] = U[s][c])
             float* Xg = Tt(t + 1 + u, t);
-            const float* Ui = U64 + 64 * o + o;
-            const f16v_t acc = prod32(gP(Xg), [=](int k2) { return gld(Ui + 64 * (2 * k2 + lh) + lr); });
+            float f[16];
+            if (t == 0) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                gst(Cp(Xg, q), acc[q]);
-                sB[res_col(q, lh) * TP + lr] = acc[q];
+                for (int c = 0; c < 32; ++c) b[c] = a_el(32 * (1 + u) + lo, c);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) b[c] = gld(Xg + lo + (int64_t)c * ldt);
             }
+#pragma unroll
+            for (int q = 0; q < 16; ++q) f[q] = gld(Fg + lo + (int64_t)(2 * q + ho) * ldt);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sA[lo * SP + 2 * q + ho] = f[q];
+            lds_order();
+#pragma unroll
+            for (int s2 = 0; s2 < 32; ++s2) {
+                float urow[32];
+#pragma unroll
+                for (int m = s2 / 4; m < 8; ++m) {
+                    const float4 v = *reinterpret_cast<const float4*>(sA + s2 * SP + 4 * m);
+                    urow[4 * m] = v.x;
+                    urow[4 * m + 1] = v.y;
+                    urow[4 * m + 2] = v.z;
+                    urow[4 * m + 3] = v.w;
+                }
+                b[s2] *= __builtin_amdgcn_rcpf(urow[s2]);
+#pragma unroll
+                for (int c = s2 + 1; c < 32; ++c) b[c] = fmaf(-b[s2], urow[c], b[c]);
+                // the step completes here: one factor row live at a time
+                pin(b[s2]);
+#pragma unroll
+                for (int c = s2 + 1; c < 32; ++c) pin(b[c]);
+            }
+            lds_order();
+            if (ho == 0) {
+#pragma unroll
+                for (int c = 0; c < 32; ++c) sB[c * TP + lo] = b[c];
+            }
+            lds_order();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) gst(Xg + lo + (int64_t)(2 * q + ho) * ldt, sB[(2 * q + ho) * TP + lo]);
+            complete(ph);
             store_final(t + 1 + u, t, sB);
         } else {
-            // tile (t,j) <- L_tt^-1 tile (t,j)  (L_tt^-1 from the column-major 64 x 64 block)
-            float* Yg = Tt(t, t + 1 + (u - w));
-            const float* Li = L64 + o + 64 * o;
-            stage_cm(sA, Yg, ldt);
-            const f16v_t acc = prod32([=](int k2) { return gld(Li + lr + 64 * (2 * k2 + lh)); }, sQ(sA));
+            // tile (t,j) <- L_tt^-1 tile (t,j): L Y = B column by column, lane
+            // r holding column r; the unit-lower L is staged column-major
+            // (sA[q*SP + s] = L[s][q])
+            const int j = t + 1 + (u - w);
+            float* Yg = Tt(t, j);
+            float f[16];
+            if (t == 0) {
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                gst(Cp(Yg, q), acc[q]);
-                sB[res_col(q, lh) * TP + lr] = acc[q];
+                for (int q = 0; q < 16; ++q) sB[(2 * q + ho) * TP + lo] = a_el(lo, 32 * j + 2 * q + ho);
+            } else {
+                stage_cm(sB, Yg, ldt, lo, ho);
             }
-            store_final(t, t + 1 + (u - w), sB);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) f[q] = gld(Fg + lo + (int64_t)(2 * q + ho) * ldt);
+#pragma unroll
+            for (int q = 0; q < 16; ++q) sA[(2 * q + ho) * SP + lo] = f[q];
+            lds_order();
+#pragma unroll
+            for (int s2 = 0; s2 < 32; ++s2) b[s2] = sB[lo * TP + s2];
+#pragma unroll
+            for (int q = 0; q < 31; ++q) {
+                float lcol[32];
+#pragma unroll
+                for (int m = (q + 1) / 4; m < 8; ++m) {
+                    const float4 v = *reinterpret_cast<const float4*>(sA + q * SP + 4 * m);
+                    lcol[4 * m] = v.x;
+                    lcol[4 * m + 1] = v.y;
+                    lcol[4 * m + 2] = v.z;
+                    lcol[4 * m + 3] = v.w;
+                }
+#pragma unroll
+                for (int s2 = q + 1; s2 < 32; ++s2) b[s2] = fmaf(-lcol[s2], b[q], b[s2]);
+#pragma unroll
+                for (int s2 = q + 1; s2 < 32; ++s2) pin(b[s2]);
+            }
+            lds_order();
+            if (ho == 0) {
+#pragma unroll
+                for (int s2 = 0; s2 < 32; ++s2) sB[lo * TP + s2] = b[s2];
+            }
+            lds_order();
+#pragma unroll
+            for (int q = 0; q < 16; ++q) gst(Yg + lo + (int64_t)(2 * q + ho) * ldt, sB[(2 * q + ho) * TP + lo]);
+            complete(ph);
+            store_final(t, j, sB);
         }
     };
 
@@ -455,17 +595,16 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
     for (; ph < NP; ++ph) {
         if (phase_target(ph, P) == 0) continue;
         if (!wait_phase(ph)) return;
-        const bool lphase = ph >= 1 && ph <= 2 * P && (ph - 1) % 2 == 0;
-        if (leader && lphase) {
-            leaf((ph - 1) / 2);
-            complete(ph);
+        if (leader && is_lphase(ph, P)) {
+            refresh();
+            leaf(ph / 2, ph);
         }
         const int nclaim = phase_claims(ph, P);
         for (;;) {
             const int u = claim(ph);
             if (u >= nclaim) break;
-            task(ph, u);
-            complete(ph);
+            refresh();
+            task(ph, u);   // counts itself done
         }
     }
 }
