@@ -618,10 +618,11 @@ static hipError_t diag_lu_typed(void* A, int64_t lda, int64_t k, int kb, int kbp
     static const hipError_t attr = hipFuncSetAttribute((const void*)k_diag_lu<ST>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_lu_smem());
     if (attr) return attr;
-    // helpers scale with the work (a 512 block: one leader and seven helpers)
+    // helpers scale with the work (a 512 block: one leader work-group and
+    // fifteen helpers; the early update phases have up to 225 tile tasks)
     const int P = kbp / 32;
-    int wgs = P / 2;
-    wgs = wgs < 1 ? 1 : (wgs > 8 ? 8 : wgs);
+    int wgs = P;
+    wgs = wgs < 1 ? 1 : (wgs > 16 ? 16 : wgs);
     k_diag_lu<ST><<<wgs, DT, diag_lu_smem(), s>>>((typename Store<ST>::T*)A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv,
                                                  sync, info);
     return hipGetLastError();

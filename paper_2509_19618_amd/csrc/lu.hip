@@ -131,22 +131,41 @@ MXP_DEV void khalf_reduce(f16v_t& acc, float* red, int blk, int kh, int lane) {
 
 // Right solve of a 32-row strip S (row i at S + i*SP): X <- S U^-1 block by
 // block, X_J = (S_J - sum_{I<J} X_I U_IJ) Uinv_J.  Urm: U11 row-major (ld),
-// uinv_rm: the 64x64 diagonal-block inverses, row-major.
-__device__ void strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ Urm, int ld,
+// uinv_rm: the 64x64 diagonal-block inverses, row-major.  The factor blocks
+// do not depend on the strip: block I+1 is loaded while block I is applied,
+// and the inverse block of step J is loaded when step J starts, so that a
+// step waits for one load latency instead of one per block.
+MXP_DEV void strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ Urm, int ld,
                                   const float* __restrict__ uinv_rm, float* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
     for (int J = 0; J < nbk; ++J) {
         const int jc = J * 64 + blk * 32 + lr;            // this lane's column of the output block
-        f16v_t acc = {};
-        for (int I = 0; I < J; ++I) {
-            const int kb0 = I * 64 + kh * 32 + lh;
-            float bv[16];
+        const int k0 = kh * 32 + lh;
+        float iv[16];
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) iv[s2] = uinv_rm[(int64_t)J * 4096 + (k0 + 2 * s2) * 64 + blk * 32 + lr];
+        auto ld_blk = [&](float* bv, int I) {
+            const int kb0 = I * 64 + k0;
 #pragma unroll
             for (int s2 = 0; s2 < 16; ++s2) bv[s2] = Urm[(int64_t)(kb0 + 2 * s2) * ld + jc];
+        };
+        f16v_t acc = {};
+        auto mf_blk = [&](const float* bv, int I) {
+            const int kb0 = I * 64 + k0;
 #pragma unroll
             for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(S[lr * SP + kb0 + 2 * s2], bv[s2], acc);
+        };
+        float b0[16], b1[16];
+        int I = 0;
+        if (J > 0) ld_blk(b0, 0);
+        for (; I + 1 < J; I += 2) {
+            ld_blk(b1, I + 1);
+            mf_blk(b0, I);
+            if (I + 2 < J) ld_blk(b0, I + 2);
+            mf_blk(b1, I + 1);
         }
+        if (I < J) mf_blk(b0, I);
         khalf_reduce(acc, red, blk, kh, lane);
         if (kh == 0)
 #pragma unroll
@@ -156,14 +175,8 @@ __device__ void strip_right_solve(float* S, int SP, int nbk, const float* __rest
             }
         __syncthreads();
         f16v_t y = {};
-        {
-            const int k0 = kh * 32 + lh;
-            float bv[16];
 #pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) bv[s2] = uinv_rm[(int64_t)J * 4096 + (k0 + 2 * s2) * 64 + blk * 32 + lr];
-#pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) y = mfma2(S[lr * SP + J * 64 + k0 + 2 * s2], bv[s2], y);
-        }
+        for (int s2 = 0; s2 < 16; ++s2) y = mfma2(S[lr * SP + J * 64 + k0 + 2 * s2], iv[s2], y);
         khalf_reduce(y, red, blk, kh, lane);
         if (kh == 0)
 #pragma unroll
@@ -177,22 +190,39 @@ __device__ void strip_right_solve(float* S, int SP, int nbk, const float* __rest
 
 // Left solve of a 32-column strip S (column j at S + j*SP): Y <- L^-1 S,
 // Y_I = Linv_I (S_I - sum_{J<I} L_IJ Y_J).  T: L11 column-major (ld),
-// linv: the 64x64 diagonal-block inverses, column-major.
-__device__ void strip_left_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ld,
+// linv: the 64x64 diagonal-block inverses, column-major.  Loads are
+// pipelined as in the right solve.
+MXP_DEV void strip_left_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ld,
                                  const float* __restrict__ linv, float* red) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
     for (int I = 0; I < nbk; ++I) {
         const int ir = I * 64 + blk * 32 + lr;            // this lane's row of L for the A operand
-        f16v_t acc = {};
-        for (int J = 0; J < I; ++J) {
-            const int kb0 = J * 64 + kh * 32 + lh;
-            float av[16];
+        const int k0 = kh * 32 + lh;
+        float iv[16];
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) iv[s2] = linv[(int64_t)I * 4096 + (blk * 32 + lr) + 64 * (k0 + 2 * s2)];
+        auto ld_blk = [&](float* av, int J) {
+            const int kb0 = J * 64 + k0;
 #pragma unroll
             for (int s2 = 0; s2 < 16; ++s2) av[s2] = T[ir + (int64_t)(kb0 + 2 * s2) * ld];
+        };
+        f16v_t acc = {};
+        auto mf_blk = [&](const float* av, int J) {
+            const int kb0 = J * 64 + k0;
 #pragma unroll
             for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(av[s2], S[lr * SP + kb0 + 2 * s2], acc);
+        };
+        float a0[16], a1[16];
+        int J = 0;
+        if (I > 0) ld_blk(a0, 0);
+        for (; J + 1 < I; J += 2) {
+            ld_blk(a1, J + 1);
+            mf_blk(a0, J);
+            if (J + 2 < I) ld_blk(a0, J + 2);
+            mf_blk(a1, J + 1);
         }
+        if (J < I) mf_blk(a0, J);
         khalf_reduce(acc, red, blk, kh, lane);
         if (kh == 0)
 #pragma unroll
@@ -202,14 +232,8 @@ __device__ void strip_left_solve(float* S, int SP, int nbk, const float* __restr
             }
         __syncthreads();
         f16v_t y = {};
-        {
-            const int k0 = kh * 32 + lh;
-            float av[16];
 #pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) av[s2] = linv[(int64_t)I * 4096 + (blk * 32 + lr) + 64 * (k0 + 2 * s2)];
-#pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) y = mfma2(av[s2], S[lr * SP + I * 64 + k0 + 2 * s2], y);
-        }
+        for (int s2 = 0; s2 < 16; ++s2) y = mfma2(iv[s2], S[lr * SP + I * 64 + k0 + 2 * s2], y);
         khalf_reduce(y, red, blk, kh, lane);
         if (kh == 0)
 #pragma unroll
