@@ -129,14 +129,30 @@ MXP_DEV void khalf_reduce(f16v_t& acc, float* red, int blk, int kh, int lane) {
         for (int q = 0; q < 16; ++q) acc[q] += red[(blk * 16 + q) * 64 + lane];
 }
 
+// maximum of v over the work-group (red: at least 4 floats of LDS, free)
+MXP_DEV float strip_max(float v, float* red) {
+    v = warp_maxf(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    const float r = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    __syncthreads();
+    return r;
+}
+
+// four consecutive elements of a storage or operand array, one access
+template <class T> struct alignas(4 * sizeof(T)) Pack4 {
+    T v[4];
+};
+
 // Right solve of a 32-row strip S (row i at S + i*SP): X <- S U^-1 block by
 // block, X_J = (S_J - sum_{I<J} X_I U_IJ) Uinv_J.  Urm: U11 row-major (ld),
 // uinv_rm: the 64x64 diagonal-block inverses, row-major.  The factor blocks
 // do not depend on the strip: block I+1 is loaded while block I is applied,
 // and the inverse block of step J is loaded when step J starts, so that a
 // step waits for one load latency instead of one per block.
-MXP_DEV void strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ Urm, int ld,
-                                  const float* __restrict__ uinv_rm, float* red) {
+MXP_DEV float strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ Urm, int ld,
+                                   const float* __restrict__ uinv_rm, float* red) {
+    float m = 0.0f;   // max |x| over this lane's final stores
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
     for (int J = 0; J < nbk; ++J) {
@@ -183,17 +199,20 @@ MXP_DEV void strip_right_solve(float* S, int SP, int nbk, const float* __restric
             for (int q = 0; q < 16; ++q) {
                 const int i = 8 * (q >> 2) + 4 * lh + (q & 3);
                 S[i * SP + jc] = y[q];
+                m = fmaxf(m, fabsf(y[q]));
             }
         __syncthreads();
     }
+    return strip_max(m, red);
 }
 
 // Left solve of a 32-column strip S (column j at S + j*SP): Y <- L^-1 S,
 // Y_I = Linv_I (S_I - sum_{J<I} L_IJ Y_J).  T: L11 column-major (ld),
 // linv: the 64x64 diagonal-block inverses, column-major.  Loads are
 // pipelined as in the right solve.
-MXP_DEV void strip_left_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ld,
-                                 const float* __restrict__ linv, float* red) {
+MXP_DEV float strip_left_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ld,
+                                  const float* __restrict__ linv, float* red) {
+    float m = 0.0f;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
     for (int I = 0; I < nbk; ++I) {
@@ -240,22 +259,11 @@ MXP_DEV void strip_left_solve(float* S, int SP, int nbk, const float* __restrict
             for (int q = 0; q < 16; ++q) {
                 const int i = I * 64 + blk * 32 + 8 * (q >> 2) + 4 * lh + (q & 3);
                 S[lr * SP + i] = y[q];
+                m = fmaxf(m, fabsf(y[q]));
             }
         __syncthreads();
     }
-}
-
-__device__ float strip_amax(const float* S, int SP, int width) {
-    __shared__ float red[4];
-    const int tid = threadIdx.x;
-    float m = 0.0f;
-    for (int e = tid; e < SR * width; e += 256) m = fmaxf(m, fabsf(S[(e / width) * SP + (e % width)]));
-    m = warp_maxf(m);
-    if ((tid & 63) == 0) red[tid >> 6] = m;
-    __syncthreads();
-    float amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    __syncthreads();
-    return amax;
+    return strip_max(m, red);
 }
 
 // LDS of a strip kernel: the strip (32 x (nb+1) floats) and the K-half reduction buffer
@@ -263,11 +271,16 @@ static inline size_t trsm_smem(int nb) { return (size_t)(SR * (nb + 1) + 2 * 16 
 
 // L21 strip: X (32 x nb) = A21[rows, :] U11^-1, then amax -> power-of-two
 // scales; writes the operand Lq (K-major, update format, scaled), the stored
-// L21 (storage format, scaled) and the scales.
+// L21 (storage format, scaled) and the scales.  A full strip moves through
+// 4-element accesses (a lane: 4 rows of one column of A, 4 columns of one
+// row of Lq), with every load of the strip in flight at once; the ragged
+// last strip takes element accesses.
 template <int ST, int OP>
-__device__ void trsm_L_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
-                             const float* __restrict__ Urm, const float* __restrict__ uinv,
-                             typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk, float* smem, int w) {
+MXP_DEV void trsm_L_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
+                          const float* __restrict__ Urm, const float* __restrict__ uinv,
+                          typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk, float* smem, int w) {
+    typedef typename Store<ST>::T STT;
+    typedef typename Operand<OP>::T OPT;
     const int SP = nb + 1;
     float* S = smem;
     float* red = smem + SR * SP;
@@ -275,35 +288,69 @@ __device__ void trsm_L_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, i
     const int64_t r0 = k + nb + (int64_t)SR * w;
     int64_t rv = n - r0;
     rv = rv > SR ? SR : (rv < 0 ? 0 : rv);
-    for (int e = tid; e < SR * nb; e += 256) {
-        int ii = e % SR, c = e / SR;
-        S[ii * SP + c] = (ii < rv) ? Store<ST>::load(A, (r0 + ii) + (k + c) * lda) : 0.0f;
+    const bool vec = rv == SR && (r0 & 3) == 0 && (lda & 3) == 0 && ((uintptr_t)A & 15) == 0;
+    const int rq = tid & 7, cg = tid >> 3;          // vector mapping: rows 4 rq.., column cg + 32 i
+    if (vec) {
+        for (int c0 = 0; c0 < nb; c0 += 512) {
+            Pack4<STT> x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int c = c0 + cg + 32 * i;
+                if (c < nb) x[i] = *(const Pack4<STT>*)(A + (r0 + 4 * rq) + (k + c) * lda);
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int c = c0 + cg + 32 * i;
+                if (c < nb)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) S[(4 * rq + q) * SP + c] = Store<ST>::load(x[i].v, q);
+            }
+        }
+    } else {
+        const int ii = tid & 31;
+        for (int c = tid >> 5; c < nb; c += 8)
+            S[ii * SP + c] = (ii < rv) ? Store<ST>::load(A, (r0 + ii) + (k + c) * lda) : 0.0f;
     }
     __syncthreads();
-    strip_right_solve(S, SP, nb / 64, Urm, nb, uinv, red);
-    const float amax = strip_amax(S, SP, nb);
+    const float amax = strip_right_solve(S, SP, nb / 64, Urm, nb, uinv, red);
     const float s_op = Operand<OP>::scaled ? pow2_scale(amax, Operand<OP>::scale_exp) : 1.0f;
     const float s_st = Store<ST>::scaled ? pow2_scale(amax, Store<ST>::scale_exp) : 1.0f;
     if (tid == 0) {
         inv_sa[w] = 1.0f / s_op;
         if (rv > 0) lsc_blk[r0 / SR] = s_st;
     }
-    for (int e = tid; e < SR * nb; e += 256) {
-        int ii = e / nb, c = e % nb;
-        Lq[((int64_t)SR * w + ii) * nb + c] = Operand<OP>::from_f32(S[ii * SP + c] * s_op);
+    // operand rows (nb contiguous values each): 4 columns per lane
+    OPT* Lw = Lq + (int64_t)SR * w * nb;
+    for (int e = 4 * tid; e < SR * nb; e += 1024) {
+        const int ii = e / nb, c = e - ii * nb;      // nb is a multiple of 64: a lane's 4 stay in one row
+        Pack4<OPT> o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o.v[q] = Operand<OP>::from_f32(S[ii * SP + c + q] * s_op);
+        *(Pack4<OPT>*)(Lw + e) = o;
     }
-    for (int e = tid; e < SR * nb; e += 256) {
-        int ii = e % SR, c = e / SR;
-        if (ii < rv) A[(r0 + ii) + (k + c) * lda] = Store<ST>::from_f32(S[ii * SP + c] * s_st);
+    if (vec) {
+        for (int c = cg; c < nb; c += 32) {
+            Pack4<STT> o;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o.v[q] = Store<ST>::from_f32(S[(4 * rq + q) * SP + c] * s_st);
+            *(Pack4<STT>*)(A + (r0 + 4 * rq) + (k + c) * lda) = o;
+        }
+    } else {
+        const int ii = tid & 31;
+        if (ii < rv)
+            for (int c = tid >> 5; c < nb; c += 8) A[(r0 + ii) + (k + c) * lda] = Store<ST>::from_f32(S[ii * SP + c] * s_st);
     }
 }
 
 // U12 strip: Y (nb x 32) = L11^-1 A12[:, cols]; operand Uq (K-major: column
-// j has nb contiguous values) scaled, stored U12 unscaled.
+// j has nb contiguous values) scaled, stored U12 unscaled.  Accesses as in
+// the L21 strip, a lane taking 4 consecutive rows of one column.
 template <int ST, int OP>
-__device__ void trsm_U_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
-                             const float* __restrict__ T, const float* __restrict__ linv,
-                             typename Operand<OP>::T* Uq, float* inv_sb, float* smem, int w) {
+MXP_DEV void trsm_U_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
+                          const float* __restrict__ T, const float* __restrict__ linv,
+                          typename Operand<OP>::T* Uq, float* inv_sb, float* smem, int w) {
+    typedef typename Store<ST>::T STT;
+    typedef typename Operand<OP>::T OPT;
     const int SP = nb + 1;
     float* S = smem;
     float* red = smem + SR * SP;
@@ -311,19 +358,55 @@ __device__ void trsm_U_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, i
     const int64_t c0 = k + nb + (int64_t)SR * w;
     int64_t cv = n - c0;
     cv = cv > SR ? SR : (cv < 0 ? 0 : cv);
-    for (int e = tid; e < SR * nb; e += 256) {
-        int kk = e % nb, cc = e / nb;
-        S[cc * SP + kk] = (cc < cv) ? Store<ST>::load(A, (k + kk) + (c0 + cc) * lda) : 0.0f;
+    // nb divides 1024: a pass covers 1024 / nb columns, a lane 4 rows
+    const int qpc = nb >> 2, lq = __builtin_ctz((unsigned)qpc);
+    const int kq = tid & (qpc - 1), cs = tid >> lq, cpp = 256 >> lq;
+    const bool vec = (1024 % nb) == 0 && (k & 3) == 0 && (lda & 3) == 0 && ((uintptr_t)A & 15) == 0;
+    if (vec) {
+        for (int p0 = 0; p0 < SR; p0 += 16 * cpp) {
+            Pack4<STT> x[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int cc = p0 + cs + cpp * i;
+                if (cc < SR && cc < cv) x[i] = *(const Pack4<STT>*)(A + (k + 4 * kq) + (c0 + cc) * lda);
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int cc = p0 + cs + cpp * i;
+                if (cc < SR)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) S[cc * SP + 4 * kq + q] = (cc < cv) ? Store<ST>::load(x[i].v, q) : 0.0f;
+            }
+        }
+    } else {
+        for (int cc = 0; cc < SR; ++cc)
+            for (int kk = tid; kk < nb; kk += 256)
+                S[cc * SP + kk] = (cc < cv) ? Store<ST>::load(A, (k + kk) + (c0 + cc) * lda) : 0.0f;
     }
     __syncthreads();
-    strip_left_solve(S, SP, nb / 64, T, nb, linv, red);
-    const float amax = strip_amax(S, SP, nb);
+    const float amax = strip_left_solve(S, SP, nb / 64, T, nb, linv, red);
     const float s_op = Operand<OP>::scaled ? pow2_scale(amax, Operand<OP>::scale_exp) : 1.0f;
     if (tid == 0) inv_sb[w] = 1.0f / s_op;
-    for (int e = tid; e < SR * nb; e += 256) {
-        int cc = e / nb, kk = e % nb;
-        Uq[((int64_t)SR * w + cc) * nb + kk] = Operand<OP>::from_f32(S[cc * SP + kk] * s_op);
-        if (cc < cv) A[(k + kk) + (c0 + cc) * lda] = Store<ST>::from_f32(S[cc * SP + kk]);
+    OPT* Uw = Uq + (int64_t)SR * w * nb;
+    if (vec) {
+        for (int cc = cs; cc < SR; cc += cpp) {
+            Pack4<OPT> o;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o.v[q] = Operand<OP>::from_f32(S[cc * SP + 4 * kq + q] * s_op);
+            *(Pack4<OPT>*)(Uw + (int64_t)cc * nb + 4 * kq) = o;
+            if (cc < cv) {
+                Pack4<STT> a;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) a.v[q] = Store<ST>::from_f32(S[cc * SP + 4 * kq + q]);
+                *(Pack4<STT>*)(A + (k + 4 * kq) + (c0 + cc) * lda) = a;
+            }
+        }
+    } else {
+        for (int cc = 0; cc < SR; ++cc)
+            for (int kk = tid; kk < nb; kk += 256) {
+                Uw[(int64_t)cc * nb + kk] = Operand<OP>::from_f32(S[cc * SP + kk] * s_op);
+                if (cc < cv) A[(k + kk) + (c0 + cc) * lda] = Store<ST>::from_f32(S[cc * SP + kk]);
+            }
     }
 }
 
