@@ -213,12 +213,14 @@ int mxp_hpl_eta(int64_t n, uint64_t seed, const double *diag, const double *a_in
  * Timing of kernel classes with HIP events recorded on the stream each
  * kernel is launched on (off by default).  Classes: 0 trailing update,
  * 1 strip TRSMs, 2 diagonal-block LU, 3 preconditioner apply, 4 regenerating
- * residual / matrix-vector product.  mxp_profile_read synchronises on the
+ * residual / matrix-vector product.  mxp_profile_enable(mask) times the
+ * classes whose bit is set in mask (0: timing off); the events add work to
+ * each timed launch's stream.  mxp_profile_read synchronises on the
  * recorded events and returns, for one class, the summed kernel time, the
  * summed algorithmic flops and bytes, and the number of timed launches
  * since the last reset.
  */
-int mxp_profile_enable(int on);
+int mxp_profile_enable(int mask);
 int mxp_profile_reset(void);
 int mxp_profile_read(int cls, double *total_ms, double *flops, double *bytes, int64_t *launches);
 

@@ -280,8 +280,12 @@ def exported_symbols():
     return [name for name, _, _ in SIGNATURES]
 
 
-def profile_enable(on: bool = True) -> None:
-    _check(lib().mxp_profile_enable(1 if on else 0))
+def profile_enable(on: bool = True, classes=None) -> None:
+    """Time the given kernel classes (PROF_*; all when None) with HIP events, or stop timing."""
+    mask = 0
+    if on:
+        mask = (1 << 6) - 1 if classes is None else sum(1 << int(c) for c in set(classes))
+    _check(lib().mxp_profile_enable(mask))
 
 
 def profile_reset() -> None:

@@ -339,7 +339,7 @@ extern "C" int mxp_trailing_update(int64_t M, int64_t N, int64_t K, int update, 
     if (M < 0 || N < 0 || K < 1 || K > 4096 || ldc < (M > 1 ? M : 1) || !valid_pair(update, store) ||
         (K * dtype_bytes(update)) % 128 || (M > 0 && N > 0 && (!C || !Aq || !Bq || !inv_sa || !inv_sb)))
         return set_err(MXP_EINVAL, "mxp_trailing_update: bad argument%s", "");
-    hipEvent_t pt = prof::begin((hipStream_t)stream);
+    hipEvent_t pt = prof::begin(prof::GEMM, (hipStream_t)stream);
     HIPCHK(gemm_update(update, store, C, ldc, M, N, (int)K, Aq, Bq, inv_sa, inv_sb, (hipStream_t)stream));
     prof::end(pt, prof::GEMM, (hipStream_t)stream, 2.0 * M * (double)N * K,
               2.0 * M * (double)N * dtype_bytes(store) + (double)(M + N) * K * dtype_bytes(update));

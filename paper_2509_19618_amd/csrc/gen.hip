@@ -203,7 +203,7 @@ hipError_t regen_matvec(int64_t n, uint64_t seed, const double* diag, const doub
     int64_t nchunk = (n + cc - 1) / cc;
     dim3 g((unsigned)((n + 255) / 256), (unsigned)nchunk);
     // the column loop steps by 4 from a chunk start that is a multiple of 4
-    hipEvent_t pt = prof::begin(s);
+    hipEvent_t pt = prof::begin(prof::REGEN, s);
     for (int r0 = 0; r0 < nr;) {
         int left = nr - r0;
         int w = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;

@@ -68,9 +68,12 @@ hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t 
 // Side stream and events of the look-ahead (default stream priority).  A
 // factorisation uses the caller's context, or a per-device one if la is NULL;
 // concurrent factorisations need a context each.
+// the critical stream of a factorisation (diagonal-block update, LU, strip
+// TRSMs) and the events that order it against the caller's stream (cross
+// update, rest of the trailing update)
 struct Lookahead {
     hipStream_t side = nullptr;
-    hipEvent_t ev_diag = nullptr, ev_cross = nullptr, ev_panel = nullptr;
+    hipEvent_t ev_upd = nullptr, ev_cross = nullptr, ev_panel = nullptr;
 };
 hipError_t lookahead_create(Lookahead* la);
 void lookahead_destroy(Lookahead* la);

@@ -482,7 +482,7 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
 hipError_t lookahead_create(Lookahead* la) {
     hipError_t e;
     if ((e = hipStreamCreateWithFlags(&la->side, hipStreamNonBlocking))) return e;
-    if ((e = hipEventCreateWithFlags(&la->ev_diag, hipEventDisableTiming))) return e;
+    if ((e = hipEventCreateWithFlags(&la->ev_upd, hipEventDisableTiming))) return e;
     if ((e = hipEventCreateWithFlags(&la->ev_cross, hipEventDisableTiming))) return e;
     return hipEventCreateWithFlags(&la->ev_panel, hipEventDisableTiming);
 }
@@ -490,7 +490,7 @@ hipError_t lookahead_create(Lookahead* la) {
 void lookahead_destroy(Lookahead* la) {
     if (la->ev_panel) hipEventDestroy(la->ev_panel);
     if (la->ev_cross) hipEventDestroy(la->ev_cross);
-    if (la->ev_diag) hipEventDestroy(la->ev_diag);
+    if (la->ev_upd) hipEventDestroy(la->ev_upd);
     if (la->side) hipStreamDestroy(la->side);
     *la = Lookahead();
 }
@@ -513,11 +513,16 @@ static hipError_t lookahead_for_device(Lookahead** out) {
 }
 
 // Right-looking blocked LU with look-ahead.  Per block step k the trailing
-// update is split into the "cross" part (block column k+1 and block row k+1)
-// and the rest; the panel of step k+1 (diagonal-block LU and strip TRSMs)
-// needs only the cross part, so it runs on the side stream while the main
-// stream performs the rest of the update.  Two operand sets alternate
-// between consecutive steps.
+// update is split into the diagonal block k+1, the rest of block column and
+// row k+1 (the "cross" part) and the rest.  The chain that sets the pace in
+// the late steps -- update of diagonal block k+1, its LU, the strip TRSMs of
+// step k+1, the next diagonal block -- runs back to back on the side stream;
+// the caller's stream performs the cross part and the rest of the update.
+// Each stream waits on the other through one event per hand-over, and in the
+// late steps each such event has fired before the wait is reached.  Two
+// operand sets alternate between consecutive steps; a set is rewritten by
+// the TRSMs of step k+2 only after the side stream has seen the update of
+// step k complete.
 template <int ST, int OP>
 static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la) {
     typedef typename Store<ST>::T ST_T;
@@ -550,7 +555,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         float* T = p.T + blk * nb * nb;
         float* linv = p.linv + blk * nb * 64;
         float* uinv = p.uinv + blk * nb * 64;
-        hipEvent_t pt = prof::begin(st);
+        hipEvent_t pt = prof::begin(prof::DIAG, st);
         hipError_t e2 = diag_lu(ST, A, lda, k, kb, kbp, T, p.Trm + blk * nb * nb, nb, linv, uinv,
                                 p.dsync + blk * diag_sync_words(), p.info, st);
         if (e2) return e2;
@@ -566,7 +571,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         const int set = (int)(blk & 1);
         const int nstrip = (int)(rup(m, 256) / SR);
         const size_t smem = trsm_smem(nb);
-        hipEvent_t pt = prof::begin(st);
+        hipEvent_t pt = prof::begin(prof::TRSM, st);
         k_trsm<ST, OP><<<2 * nstrip, 256, smem, st>>>(A, lda, n, k, nb, nstrip, p.Trm + blk * nb * nb,
                                                        p.uinv + blk * nb * 64, p.T + blk * nb * nb,
                                                        p.linv + blk * nb * 64, (OP_T*)p.Lq + set * opset,
@@ -585,7 +590,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         const float* sa = p.inv_sa + set * scset;
         const float* sb = p.inv_sb + set * scset;
         ST_T* C = A + (k + nb + c0) + (k + nb + c1) * lda;
-        hipEvent_t pt = prof::begin(st);
+        hipEvent_t pt = prof::begin(prof::GEMM, st);
         hipError_t e2 = gemm_update(OP, ST, C, lda, M, N, nb, Lq + c0 * nb, Uq + c1 * nb, sa + c0 / 32, sb + c1 / 32,
                                     st);
         prof::end(pt, prof::GEMM, st, 2.0 * M * (double)N * nb,
@@ -607,36 +612,45 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     }
     if ((e = diag(0, s))) return e;
     if ((e = trsm(0, s))) return e;
+    // side stream: panel 0 and the untouched trailing matrix are ready
+    if ((e = hipEventRecord(LA->ev_upd, s))) return e;
+    bool side_used = false;
     for (int64_t k = 0; k + nb < n; k += nb) {
         const int64_t m = n - k - nb;               // trailing size after step k
         if (m > nb) {
-            // the next diagonal block first, so that its LU starts on the side
-            // stream at once; then the rest of block column and row k+1, which
-            // the next strip TRSMs need; the main stream goes on with the rest
             const int64_t c = nb;
-            if ((e = gemm(k, 0, 0, c, c, s))) return e;
-            if ((e = hipEventRecord(LA->ev_diag, s))) return e;
-            if ((e = hipStreamWaitEvent(LA->side, LA->ev_diag, 0))) return e;
+            // side: diagonal block k+1 (needs the update of step k-1 and panel k), its LU
+            if ((e = hipStreamWaitEvent(LA->side, LA->ev_upd, 0))) return e;
+            if ((e = gemm(k, 0, 0, c, c, LA->side))) return e;
             if ((e = diag(k + nb, LA->side))) return e;
+            // main: the rest of block column and row k+1 (needs panel k)
+            if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
             if ((e = gemm(k, c, 0, m - c, c, s))) return e;
             if ((e = gemm(k, 0, c, c, m - c, s))) return e;
             if ((e = hipEventRecord(LA->ev_cross, s))) return e;
+            // side: panel k+1
             if ((e = hipStreamWaitEvent(LA->side, LA->ev_cross, 0))) return e;
             if ((e = trsm(k + nb, LA->side))) return e;
             if ((e = hipEventRecord(LA->ev_panel, LA->side))) return e;
+            side_used = true;
+            // main: the rest of the update of step k
             if ((e = update(k, 2, s))) return e;
-            if ((e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
+            if ((e = hipEventRecord(LA->ev_upd, s))) return e;
         } else {
+            if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
+            side_used = false;
             if ((e = update(k, 0, s))) return e;
             if ((e = diag(k + nb, s))) return e;
             if ((e = trsm(k + nb, s))) return e;
         }
     }
+    // the caller's stream ends after every side-stream kernel
+    if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
     // full FP32 inverses of every diagonal block, used by the preconditioner
     {
         const int64_t nblk = (n + nb - 1) / nb;
         dim3 g((unsigned)(nb / SR), (unsigned)nblk);
-        hipEvent_t pt = prof::begin(s);
+        hipEvent_t pt = prof::begin(prof::DIAG, s);
         k_inv_upper<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.Trm, p.uinv, p.uinv_full);
         k_inv_lower<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.T, p.linv, p.linv_full);
         prof::end(pt, prof::DIAG, s, 2.0 / 3.0 * (double)n * nb * nb, 16.0 * (double)n * nb);

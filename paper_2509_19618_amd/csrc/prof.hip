@@ -16,7 +16,7 @@ struct Rec {
 };
 
 static std::mutex g_mu;
-static bool g_on = false;
+static int g_mask = 0;                   // bit c: class c is timed
 static std::vector<hipEvent_t> g_pool;   // free events
 static std::vector<Rec> g_pending;       // recorded, not yet collected
 static double g_ms[NCLS], g_flops[NCLS], g_bytes[NCLS];
@@ -33,10 +33,10 @@ static hipEvent_t take() {
     return e;
 }
 
-bool enabled() { return g_on; }
+bool enabled() { return g_mask != 0; }
 
-hipEvent_t begin(hipStream_t s) {
-    if (!g_on) return nullptr;
+hipEvent_t begin(Cls c, hipStream_t s) {
+    if (!(g_mask >> (int)c & 1)) return nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
     hipEvent_t a = take();
     if (a) hipEventRecord(a, s);
@@ -44,7 +44,7 @@ hipEvent_t begin(hipStream_t s) {
 }
 
 void end(hipEvent_t a, Cls c, hipStream_t s, double flops, double bytes) {
-    if (!g_on || !a) return;
+    if (!a) return;
     std::lock_guard<std::mutex> lk(g_mu);
     hipEvent_t b = take();
     if (!b) { g_pool.push_back(a); return; }
@@ -57,9 +57,9 @@ void end(hipEvent_t a, Cls c, hipStream_t s, double flops, double bytes) {
 
 using namespace mxp::prof;
 
-extern "C" int mxp_profile_enable(int on) {
+extern "C" int mxp_profile_enable(int mask) {
     std::lock_guard<std::mutex> lk(g_mu);
-    g_on = on != 0;
+    g_mask = mask & ((1 << NCLS) - 1);
     return MXP_OK;
 }
 

@@ -13,9 +13,9 @@ namespace prof {
 enum Cls : int { GEMM = 0, TRSM = 1, DIAG = 2, PREC = 3, REGEN = 4, GMRES = 5, NCLS = 6 };
 
 bool enabled();
-// begin() records a start event on s and returns it (nullptr when timing is
-// off); end() records the matching stop event on the same stream.
-hipEvent_t begin(hipStream_t s);
+// begin() records a start event on s and returns it (nullptr when timing of
+// class c is off); end() records the matching stop event on the same stream.
+hipEvent_t begin(Cls c, hipStream_t s);
 void end(hipEvent_t start, Cls c, hipStream_t s, double flops, double bytes);
 
 }  // namespace prof

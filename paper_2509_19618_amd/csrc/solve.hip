@@ -245,7 +245,7 @@ static hipError_t prec_typed(const PrecPlan& p, const double* V, int64_t ldv, do
     unsigned* flags = (unsigned*)(Tb + n);
     int* err = prec_err_word(W, n, nr);
     const int vec = ((p.lda * (int64_t)sizeof(T)) % 16 == 0 && ((uintptr_t)p.A) % 16 == 0) ? 1 : 0;
-    hipEvent_t pt = prof::begin(s);
+    hipEvent_t pt = prof::begin(prof::PREC, s);
     k_scale_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, p.rowscale, V, ldv, R, nr);
     for (int r = 0; r < nr; ++r) {
         k_zero_u32<<<(unsigned)((4 * J + 255) / 256), 256, 0, s>>>(flags, 4 * J);
