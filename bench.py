@@ -185,7 +185,8 @@ def summarize_stats(args):
     os.makedirs(PROFILES, exist_ok=True)
     fn = os.path.join(PROFILES, "kernel_stats_n%d_nb%d_%s_%s.txt" % (args.n, args.nb, args.update, args.store))
     with open(fn, "w") as f:
-        f.write("# rocprofv3 --kernel-trace --stats summary, one timed bench step (n=%d nb=%d %s/%s)\n"
+        f.write("# rocprofv3 --kernel-trace --stats summary of bench.py --steps 1 --warmup 1 (n=%d nb=%d %s/%s):\n"
+                "# three solves: the warm-up step, the timed step and the per-phase timing step\n"
                 % (args.n, args.nb, args.update, args.store))
         f.write("# command: %s\n" % args.cmd)
         f.write("%-60s %7s %12s %12s %7s\n" % ("kernel", "calls", "total_ms", "avg_us", "pct"))
