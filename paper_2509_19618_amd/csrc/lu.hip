@@ -292,11 +292,14 @@ MXP_DEV void trsm_L_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int6
     const int rq = tid & 7, cg = tid >> 3;          // vector mapping: rows 4 rq.., column cg + 32 i
     if (vec) {
         for (int c0 = 0; c0 < nb; c0 += 512) {
+            // loads without conditions (a column past nb reads column 0,
+            // unused): a load under a branch ends in a wait for every load in
+            // flight, which would serialise them
             Pack4<STT> x[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int c = c0 + cg + 32 * i;
-                if (c < nb) x[i] = *(const Pack4<STT>*)(A + (r0 + 4 * rq) + (k + c) * lda);
+                x[i] = *(const Pack4<STT>*)(A + (r0 + 4 * rq) + (k + (c < nb ? c : 0)) * lda);
             }
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
@@ -364,11 +367,14 @@ MXP_DEV void trsm_U_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int6
     const bool vec = (1024 % nb) == 0 && (k & 3) == 0 && (lda & 3) == 0 && ((uintptr_t)A & 15) == 0;
     if (vec) {
         for (int p0 = 0; p0 < SR; p0 += 16 * cpp) {
+            // loads without conditions, as in the L21 strip (a column past the
+            // matrix reads column k + nb, unused)
             Pack4<STT> x[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
                 const int cc = p0 + cs + cpp * i;
-                if (cc < SR && cc < cv) x[i] = *(const Pack4<STT>*)(A + (k + 4 * kq) + (c0 + cc) * lda);
+                const int64_t col = (cc < SR && cc < cv) ? c0 + cc : k + nb;
+                x[i] = *(const Pack4<STT>*)(A + (k + 4 * kq) + col * lda);
             }
 #pragma unroll
             for (int i = 0; i < 16; ++i) {

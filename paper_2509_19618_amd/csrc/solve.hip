@@ -48,6 +48,29 @@ constexpr int TS = 64;
 MXP_DEV void put_shared(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 MXP_DEV double get_shared(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
+// v, treated as written at this point: arithmetic on prefetched registers
+// cannot move above it (the compiler would otherwise unpack a load's result
+// right after issuing it, which waits for the load)
+MXP_DEV void pin4(uint4& v) { asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w)); }
+
+// element k of a 16-byte vector of storage values, taken from its 32-bit
+// words (no access through a cast pointer, which would split the vector at
+// its load)
+template <int ST> MXP_DEV float u4_elem(const uint4& v, int k);
+template <> MXP_DEV float u4_elem<F32>(const uint4& v, int k) {
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    return __uint_as_float(w[k]);
+}
+template <> MXP_DEV float u4_elem<F16>(const uint4& v, int k) {
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    const unsigned h = (k & 1) ? (w[k >> 1] >> 16) : (w[k >> 1] & 0xFFFFu);
+    return (float)__builtin_bit_cast(_Float16, (unsigned short)h);
+}
+template <> MXP_DEV float u4_elem<BF16>(const uint4& v, int k) {
+    const unsigned w[4] = {v.x, v.y, v.z, v.w};
+    return __uint_as_float((k & 1) ? (w[k >> 1] & 0xFFFF0000u) : (w[k >> 1] << 16));
+}
+
 __device__ bool wait_flag(const unsigned* flag, unsigned target, int* err, int* s_abort) {
     if (threadIdx.x == 0) {
         int ok = 1;
@@ -111,16 +134,22 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
         const int kbi = (int)(n - c0 < nb ? n - c0 : nb);
         const int q = (kbi + 3) / 4, cb = wv * q, ce = (cb + q < kbi) ? cb + q : kbi;
         const T* base = A + r0 + RPL * rg + c0 * lda;
-        // the factor panel does not depend on the flag: its loads overlap the wait
+        // the factor panel does not depend on the flag: its loads overlap the
+        // wait.  The loads carry no condition (a column past the range reads
+        // column 0 and is weighted zero below): a load under a branch ends in
+        // a wait for every load in flight, which would serialise them
+        // (the ragged last strip, which takes element loads below, reads the
+        // 16-byte aligned inverse array instead and ignores the values)
         uint4 pre[PF];
-        if (vload) {
 #pragma unroll
-            for (int m = 0; m < PF; ++m) {
-                const int c = cb + cl + m * CPI;
-                if (c < ce) pre[m] = *(const uint4*)(base + (int64_t)c * lda);
-            }
+        for (int m = 0; m < PF; ++m) {
+            const int c = cb + cl + m * CPI;
+            const void* src = vload ? (const void*)(base + (int64_t)(c < ce ? c : 0) * lda) : (const void*)inv_all;
+            pre[m] = *(const uint4*)src;
         }
         if (!wait_flag(&ready[i], strips_of(i), err, &s_abort)) return;
+#pragma unroll
+        for (int m = 0; m < PF; ++m) pin4(pre[m]);
         for (int c = tid; c < kbi; c += 256) zs[c] = get_shared(out + c0 + c);
         __syncthreads();
         double acc[RPL];
@@ -130,12 +159,9 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
 #pragma unroll
             for (int m = 0; m < PF; ++m) {
                 const int c = cb + cl + m * CPI;
-                if (c < ce) {
-                    const T* e = (const T*)&pre[m];
-                    const double zc = zs[c];
+                const double zc = c < ce ? zs[c] : 0.0;
 #pragma unroll
-                    for (int k = 0; k < RPL; ++k) acc[k] += (double)Store<ST>::load(e, k) * zc;
-                }
+                for (int k = 0; k < RPL; ++k) acc[k] += (double)u4_elem<ST>(pre[m], k) * zc;
             }
 #pragma unroll 4
             for (int c = cb + cl + PF * CPI; c < ce; c += CPI) {
@@ -182,14 +208,27 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
         const int rsub = lane % 16, csub = lane / 16;
         const float* colbase = inv_all + j * (int64_t)nb * nb + rl0 + 4 * rsub;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
-        for (int c = cb + csub; c < ce; c += 4) {
-            const float4 v = *(const float4*)(colbase + (int64_t)c * nb);
-            const double zc = zs[c];
+        auto fma4 = [&](const float4 v, double zc) {
             acc[0] += (double)v.x * zc;
             acc[1] += (double)v.y * zc;
             acc[2] += (double)v.z * zc;
             acc[3] += (double)v.w * zc;
+        };
+        // batches of NIV loads in flight at once, without conditions (a
+        // column past the range reads column clo and is weighted zero)
+        constexpr int NIV = 16;
+        for (int c0b = cb + csub; c0b < ce; c0b += 4 * NIV) {
+            float4 iv[NIV];
+#pragma unroll
+            for (int t = 0; t < NIV; ++t) {
+                const int c = c0b + 4 * t;
+                iv[t] = *(const float4*)(colbase + (int64_t)(c < ce ? c : clo) * nb);
+            }
+#pragma unroll
+            for (int t = 0; t < NIV; ++t) {
+                const int c = c0b + 4 * t;
+                fma4(iv[t], c < ce ? zs[c] : 0.0);
+            }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) part[wv][csub][4 * rsub + k] = acc[k];
