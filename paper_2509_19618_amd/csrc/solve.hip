@@ -52,6 +52,7 @@ MXP_DEV double get_shared(const double* p) { return __hip_atomic_load(p, __ATOMI
 // cannot move above it (the compiler would otherwise unpack a load's result
 // right after issuing it, which waits for the load)
 MXP_DEV void pin4(uint4& v) { asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w)); }
+MXP_DEV void pin4f(float4& v) { asm volatile("" : "+v"(v.x), "+v"(v.y), "+v"(v.z), "+v"(v.w)); }
 
 // element k of a 16-byte vector of storage values, taken from its 32-bit
 // words (no access through a cast pointer, which would split the vector at
@@ -190,23 +191,37 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
             w[tid] -= t;
         }
     }
+    // this strip's rows of the diagonal-block inverse (lower / upper
+    // triangular: only the columns up to / from the strip's rows), four rows
+    // per lane with 16-byte loads, the waves splitting the columns.  They do
+    // not depend on the other strips: the first batch is loaded while the
+    // strips of the block meet.
+    const int64_t cj = j * nb;
+    const int kbj = (int)(n - cj < nb ? n - cj : nb);
+    const int rl0 = (int)(r0 - cj);
+    const int clo = LOWER ? 0 : rl0, chi = LOWER ? (rl0 + TS < kbj ? rl0 + TS : kbj) : kbj;
+    const int qv = (chi - clo + 3) / 4, cbv = clo + wv * qv, cev = (cbv + qv < chi) ? cbv + qv : chi;
+    const int rsub = lane % 16, csub = lane / 16;
+    const float* colbase = inv_all + j * (int64_t)nb * nb + rl0 + 4 * rsub;
     // this strip's rows of the block right-hand side are final
     if (tid < rows) put_shared(tbuf + r0 + tid, w[tid]);
     signal_flag(&cnt[j]);
+    // (issued after the signal, whose wait for this wave's stores would also
+    // wait for them)
+    constexpr int NIV = 16;
+    float4 iv0[NIV];
+#pragma unroll
+    for (int t = 0; t < NIV; ++t) {
+        const int c = cbv + csub + 4 * t;
+        iv0[t] = *(const float4*)(colbase + (int64_t)(c < cev ? c : clo) * nb);
+    }
     if (!wait_flag(&cnt[j], strips_of(j), err, &s_abort)) return;
-    const int64_t cj = j * nb;
-    const int kbj = (int)(n - cj < nb ? n - cj : nb);
+#pragma unroll
+    for (int t = 0; t < NIV; ++t) pin4f(iv0[t]);
     for (int c = tid; c < kbj; c += 256) zs[c] = get_shared(tbuf + cj + c);
     __syncthreads();
-    // this strip's rows of the diagonal-block inverse (lower / upper
-    // triangular: only the columns up to / from the strip's rows), four rows
-    // per lane with 16-byte loads, the waves splitting the columns
     {
-        const int rl0 = (int)(r0 - cj);
-        const int clo = LOWER ? 0 : rl0, chi = LOWER ? (rl0 + TS < kbj ? rl0 + TS : kbj) : kbj;
-        const int q = (chi - clo + 3) / 4, cb = clo + wv * q, ce = (cb + q < chi) ? cb + q : chi;
-        const int rsub = lane % 16, csub = lane / 16;
-        const float* colbase = inv_all + j * (int64_t)nb * nb + rl0 + 4 * rsub;
+        const int cb = cbv, ce = cev;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         auto fma4 = [&](const float4 v, double zc) {
             acc[0] += (double)v.x * zc;
@@ -214,10 +229,15 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
             acc[2] += (double)v.z * zc;
             acc[3] += (double)v.w * zc;
         };
-        // batches of NIV loads in flight at once, without conditions (a
-        // column past the range reads column clo and is weighted zero)
-        constexpr int NIV = 16;
-        for (int c0b = cb + csub; c0b < ce; c0b += 4 * NIV) {
+#pragma unroll
+        for (int t = 0; t < NIV; ++t) {
+            const int c = cb + csub + 4 * t;
+            fma4(iv0[t], c < ce ? zs[c] : 0.0);
+        }
+        // the rest in batches of NIV loads in flight at once, without
+        // conditions (a column past the range reads column clo and is
+        // weighted zero)
+        for (int c0b = cb + csub + 4 * NIV; c0b < ce; c0b += 4 * NIV) {
             float4 iv[NIV];
 #pragma unroll
             for (int t = 0; t < NIV; ++t) {
