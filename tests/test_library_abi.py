@@ -86,3 +86,23 @@ def test_server_request_bytes_and_argument_checks():
     cfg = mxp._ServerCfg(2, mxp.BF16, mxp.BF16, 96, 0, 30, 50, 16.0, 2.0 ** -50)
     assert L.mxp_server_create(0, ctypes.c_void_p(256), 1 << 20, ctypes.byref(cfg), ctypes.byref(h)) == mxp.EINVAL
     assert L.mxp_server_submit(None, 512, 1, 1, None, ctypes.byref(ctypes.c_uint64())) == mxp.EINVAL
+
+
+def test_profile_classes_mask_and_read_without_device_work():
+    """mxp_profile_enable takes a bitmask of kernel classes; reading a class
+    with nothing timed returns zeros, an unknown class is rejected (no HIP
+    call is made by any of these)."""
+    L = ctypes.CDLL(mxp.LIB_PATH)
+    L.mxp_profile_read.argtypes = [ctypes.c_int] + [ctypes.c_void_p] * 4
+    assert L.mxp_profile_reset() == 0
+    assert L.mxp_profile_enable(1 << mxp.PROF_GEMM) == 0
+    ms, fl, by = ctypes.c_double(-1), ctypes.c_double(-1), ctypes.c_double(-1)
+    cnt = ctypes.c_int64(-1)
+    args = [ctypes.addressof(ms), ctypes.addressof(fl), ctypes.addressof(by), ctypes.addressof(cnt)]
+    assert L.mxp_profile_read(mxp.PROF_TRSM, *args) == 0
+    assert (ms.value, fl.value, by.value, cnt.value) == (0.0, 0.0, 0.0, 0)
+    assert L.mxp_profile_read(99, *args) != 0
+    assert L.mxp_profile_read(-1, *args) != 0
+    assert L.mxp_profile_enable(0) == 0
+    mxp.profile_enable(True, classes=[mxp.PROF_GEMM, mxp.PROF_DIAG])
+    mxp.profile_enable(False)
