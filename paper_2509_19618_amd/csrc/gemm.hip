@@ -98,7 +98,7 @@ template <> struct Quad<BF16> {
 // Work-group tile TM x TN = 256 x 128, 4 waves in a 2 x 2 grid, each wave
 // 128 x 64 (8 blocks of 32 x 32, accumulators in AGPRs).  Two work-groups
 // share a CU (at most 256 registers per wave, 72 KB of LDS each), so that
-// one work-group's epilogue (HBM-bound) overlaps the other's MFMA loop.
+// one work-group's epilogue overlaps the other's MFMA loop.
 constexpr int TM = 256, TN = 128;
 constexpr int GBK = 64;            // K bytes per stage
 constexpr int NBUF = 3;            // stages in LDS: two copies in flight while one is read
@@ -112,8 +112,23 @@ MXP_DEV void dma16(const char* g, char* l) {
     __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1)))*)g,
                                      (void __attribute__((address_space(3)))*)l, 16, 0, 0);
 }
-// s_waitcnt vmcnt(N) (expcnt / lgkmcnt not waited); N < 16
-template <int N> MXP_DEV void wait_vm() { __builtin_amdgcn_s_waitcnt((N & 0xF) | (0x7 << 4) | (0xF << 8)); }
+// s_waitcnt vmcnt(N) (expcnt / lgkmcnt not waited); N < 64
+template <int N> MXP_DEV void wait_vm() {
+    static_assert(N < 64, "vmcnt has six bits");
+    __builtin_amdgcn_s_waitcnt((N & 0xF) | (0x7 << 4) | (0xF << 8) | ((N >> 4) << 14));
+}
+// wait_vm<y NIS + (c ? NC : 0)> for a wave-uniform y <= Y
+template <int NIS, int NC, int Y> MXP_DEV void wait_case(int y, bool c) {
+    if constexpr (Y >= 0) {
+        if (y == Y) {
+            if (c) wait_vm<Y * NIS + NC>();
+            else wait_vm<Y * NIS>();
+            return;
+        }
+        wait_case<NIS, NC, Y - 1>(y, c);
+    }
+}
+
 
 // byte offset of (row, byte b) in an operand stage: 16-byte chunks XOR-swizzled by row
 MXP_DEV int swz(int row, int b) { return row * GBK + ((((b >> 4) ^ (row & (GCH - 1))) << 4) | (b & 15)); }
@@ -148,12 +163,15 @@ template <> struct Frag<F8> {
 };
 
 // Operands: K-major rows, copied GBK bytes of K per stage straight into
-// XOR-swizzled LDS buffers (no staging registers), NBUF stages deep; the
-// fragments of k-step ks+1 are read from LDS while the MFMAs of k-step ks
-// run.  Epilogue, full tiles with 16-bit C: the freed LDS holds the C tile
-// (read and written with coalesced 16-byte accesses, 512 bytes per column),
-// updated in place in the MFMA layout; other tiles update C directly with
-// guarded accesses.
+// XOR-swizzled LDS buffers (no staging registers), NBUF stages deep; each
+// k-step reads its fragments from LDS (the other work-group on the SIMD
+// covers their latency).  Epilogue, full tiles with 16-bit C: the freed LDS
+// holds the C tile (read and written with coalesced 16-byte accesses, 512
+// bytes per column), updated in place in the MFMA layout; the first half of
+// the tile is loaded into registers at the first stage, so that its HBM
+// reads overlap the MFMA loop (the whole tile would not fit beside the
+// accumulators), the second half in the epilogue.  Other tiles update C
+// directly with guarded accesses.
 template <int OP, int ST>
 __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C, int64_t ldc, int64_t M, int64_t N,
                                                         int K, const char* __restrict__ Aq,
@@ -215,62 +233,55 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+    const bool full = vec_ok && (row0 + TM <= M) && (col0 + TN <= N);
+    constexpr bool c16 = sizeof(CT) == 2;
+    const bool cpre = c16 && full;
+    constexpr int COLB = TM * 2;           // bytes of a tile column
+    constexpr int LPC = COLB / 16;         // lanes per column
+    constexpr int CPI = 64 / LPC;          // columns per wave instruction
+    constexpr int NIT = TN / 4 / CPI;      // instructions per wave
+    const int lc = lane / LPC, lo = (lane % LPC) * 16;
+    i4v xv[NIT];                           // the C tile, 16 bytes per register quad
 #pragma unroll
     for (int st = 0; st < NBUF - 1; ++st)
         if (st < nst) issue(st);
     for (int st = 0; st < nst; ++st) {
-        // stage st has landed when at most the younger stage's copies are outstanding
-        if (st + 1 < nst) wait_vm<NIS>();
-        else wait_vm<0>();
+        // stage st has landed when at most the younger stages' copies are
+        // outstanding, and the C loads while they are younger than stage st
+        // (issued at stage 0, after the copies of stages up to NBUF - 1)
+        const int younger = (NBUF - 2) < (nst - 1 - st) ? (NBUF - 2) : (nst - 1 - st);
+        const bool cy = cpre && st > 0 && st <= NBUF - 1;
+        wait_case<NIS, NIT / 2, NBUF - 2>(younger, cy);
         __syncthreads();                  // stage st visible to all; stage st-1's buffer free
         if (st + NBUF - 1 < nst) issue(st + NBUF - 1);
+        if (cpre && st == 0) {
+#pragma unroll
+            for (int it = 0; it < NIT / 2; ++it) {
+                const int c = (wave * NIT + it) * CPI + lc;
+                xv[it] = __builtin_nontemporal_load((const i4v*)((const char*)(C + row0 + (col0 + c) * ldc) + lo));
+            }
+        }
         const char* A0 = sA + (st % NBUF) * SA;
         const char* B0 = sB + (st % NBUF) * SB;
-        FT ac[4], bc[2];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) ac[a] = Frag<OP>::ld(A0, wm * 128 + a * 32 + lr, lh * (KB / 2));
-#pragma unroll
-        for (int b = 0; b < 2; ++b) bc[b] = Frag<OP>::ld(B0, wn * 64 + b * 32 + lr, lh * (KB / 2));
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
-            FT an[4], bn[2];
-            if (ks + 1 < NKS) {
-                const int boff = (ks + 1) * KB + lh * (KB / 2);
+            FT ac[4], bc[2];
+            const int boff = ks * KB + lh * (KB / 2);
 #pragma unroll
-                for (int a = 0; a < 4; ++a) an[a] = Frag<OP>::ld(A0, wm * 128 + a * 32 + lr, boff);
+            for (int a = 0; a < 4; ++a) ac[a] = Frag<OP>::ld(A0, wm * 128 + a * 32 + lr, boff);
 #pragma unroll
-                for (int b = 0; b < 2; ++b) bn[b] = Frag<OP>::ld(B0, wn * 64 + b * 32 + lr, boff);
-            }
+            for (int b = 0; b < 2; ++b) bc[b] = Frag<OP>::ld(B0, wn * 64 + b * 32 + lr, boff);
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) acc[a][b] = Frag<OP>::mma(ac[a], bc[b], acc[a][b]);
-            if (ks + 1 < NKS) {
-                // interleave the LDS reads of the next k-step with these MFMAs
-#pragma unroll
-                for (int q = 0; q < 6; ++q) {
-                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                    __builtin_amdgcn_sched_group_barrier(0x100, OP == F8 ? 2 : 1, 0);
-                }
-#pragma unroll
-                for (int a = 0; a < 4; ++a) ac[a] = an[a];
-#pragma unroll
-                for (int b = 0; b < 2; ++b) bc[b] = bn[b];
-            }
         }
     }
-    const bool full = vec_ok && (row0 + TM <= M) && (col0 + TN <= N);
     if constexpr (sizeof(CT) == 2) {
         if (full) {
-            constexpr int COLB = TM * 2;           // bytes of a tile column
-            constexpr int LPC = COLB / 16;         // lanes per column
-            constexpr int CPI = 64 / LPC;          // columns per wave instruction
-            constexpr int NIT = TN / 4 / CPI;      // instructions per wave
-            const int lc = lane / LPC, lo = (lane % LPC) * 16;
             __syncthreads();                       // operand buffers no longer read
-            i4v xv[NIT];
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) {
+            for (int it = NIT / 2; it < NIT; ++it) {
                 const int c = (wave * NIT + it) * CPI + lc;
                 xv[it] = __builtin_nontemporal_load((const i4v*)((const char*)(C + row0 + (col0 + c) * ldc) + lo));
             }
