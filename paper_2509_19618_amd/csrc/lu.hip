@@ -494,10 +494,10 @@ hipError_t lookahead_create(Lookahead* la) {
 }
 
 void lookahead_destroy(Lookahead* la) {
-    if (la->ev_panel) hipEventDestroy(la->ev_panel);
-    if (la->ev_cross) hipEventDestroy(la->ev_cross);
-    if (la->ev_upd) hipEventDestroy(la->ev_upd);
-    if (la->side) hipStreamDestroy(la->side);
+    if (la->ev_panel) (void)hipEventDestroy(la->ev_panel);
+    if (la->ev_cross) (void)hipEventDestroy(la->ev_cross);
+    if (la->ev_upd) (void)hipEventDestroy(la->ev_upd);
+    if (la->side) (void)hipStreamDestroy(la->side);
     *la = Lookahead();
 }
 

@@ -39,7 +39,11 @@ hipEvent_t begin(Cls c, hipStream_t s) {
     if (!(g_mask >> (int)c & 1)) return nullptr;
     std::lock_guard<std::mutex> lk(g_mu);
     hipEvent_t a = take();
-    if (a) hipEventRecord(a, s);
+    // a record that fails leaves the launch untimed
+    if (a && hipEventRecord(a, s) != hipSuccess) {
+        g_pool.push_back(a);
+        return nullptr;
+    }
     return a;
 }
 
@@ -47,8 +51,11 @@ void end(hipEvent_t a, Cls c, hipStream_t s, double flops, double bytes) {
     if (!a) return;
     std::lock_guard<std::mutex> lk(g_mu);
     hipEvent_t b = take();
-    if (!b) { g_pool.push_back(a); return; }
-    hipEventRecord(b, s);
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+        g_pool.push_back(a);
+        if (b) g_pool.push_back(b);
+        return;
+    }
     g_pending.push_back({(int)c, a, b, flops, bytes});
 }
 

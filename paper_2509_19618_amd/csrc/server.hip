@@ -203,7 +203,8 @@ int run_request(mxp_server* S, mxp_server::Slot& sl, Req* r) {
 
 void slot_main(mxp_server* S, int k) {
     mxp_server::Slot& sl = S->slots[(size_t)k];
-    hipSetDevice(S->device);
+    // a slot that cannot select the server's device fails every request it takes
+    const bool dev_ok = hipSetDevice(S->device) == hipSuccess;
     for (;;) {
         Req* r = nullptr;
         {
@@ -223,7 +224,7 @@ void slot_main(mxp_server* S, int k) {
             S->peak_in_flight = std::max(S->peak_in_flight, S->in_flight);
             S->peak_bytes = std::max(S->peak_bytes, S->arena.used());
         }
-        const int rc = run_request(S, sl, r);
+        const int rc = dev_ok ? run_request(S, sl, r) : MXP_EHIP;
         {
             std::lock_guard<std::mutex> lock(S->mu);
             S->arena.release(r->off, r->bytes);
@@ -245,7 +246,10 @@ void autotune(mxp_server* S) {
     const mxp_server_cfg& c = S->cfg;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return;
-    if (hipEventCreate(&e1) != hipSuccess) { hipEventDestroy(e0); return; }
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return;
+    }
     for (int cls = 0; cls < NCLASS; ++cls) {
         const int64_t n = 512ll << cls;
         float best = 0;
@@ -261,7 +265,7 @@ void autotune(mxp_server* S) {
                 char* b = S->base;
                 if (mxp_generate(n, 1, r.seed, c.store, b + L.A, L.lda, (double*)(b + L.B), n, (double*)(b + L.diag),
                                  (double*)(b + L.ainf), sl.s)) { ok = false; break; }
-                hipEventRecord(e0, sl.s);
+                if (hipEventRecord(e0, sl.s) != hipSuccess) { ok = false; break; }
                 int64_t info = 0;
                 std::vector<mxp_rhs_report> q(1);
                 int rc = factor_with(n, nb, c.update, c.store, MXP_SCALE_NONE, (double*)(b + L.diag), b + L.A, L.lda,
@@ -271,10 +275,12 @@ void autotune(mxp_server* S) {
                                       (double*)(b + L.diag), (double*)(b + L.ainf), (double*)(b + L.B), n,
                                       (double*)(b + L.X), n, 1, c.restart, c.max_iters, c.tol, c.tau, q.data(),
                                       b + L.swork, L.swork_bytes, sl.s);
-                hipEventRecord(e1, sl.s);
-                if (rc != MXP_OK || hipEventSynchronize(e1) != hipSuccess) { ok = false; break; }
+                if (rc != MXP_OK || hipEventRecord(e1, sl.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    ok = false;
+                    break;
+                }
                 float ms = 0;
-                hipEventElapsedTime(&ms, e0, e1);
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { ok = false; break; }
                 if (rep > 0 && (ms_min == 0 || ms < ms_min)) ms_min = ms;   // the first run warms up
             }
             if (ok && (best == 0 || ms_min < best)) {
@@ -283,8 +289,8 @@ void autotune(mxp_server* S) {
             }
         }
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
 }
 
 }  // namespace
@@ -320,13 +326,13 @@ extern "C" int mxp_server_create(int device, void* arena, size_t arena_bytes, co
     if (rc != MXP_OK) {
         for (auto& sl : S->slots) {
             lookahead_destroy(&sl.la);
-            if (sl.s) hipStreamDestroy(sl.s);
+            if (sl.s) (void)hipStreamDestroy(sl.s);
         }
-        hipSetDevice(prev);
+        (void)hipSetDevice(prev);   // restores the caller's device
         return rc;
     }
     for (int k = 0; k < cfg->max_slots; ++k) S->slots[(size_t)k].th = std::thread(slot_main, S.get(), k);
-    hipSetDevice(prev);
+    (void)hipSetDevice(prev);
     *out = S.release();
     return MXP_OK;
 }
@@ -423,14 +429,16 @@ extern "C" int mxp_server_destroy(mxp_server* S) {
     S->cv_work.notify_all();
     for (auto& sl : S->slots)
         if (sl.th.joinable()) sl.th.join();
+    // teardown: the streams and events are released on the server's device,
+    // whatever those calls return
     int prev = 0;
-    hipGetDevice(&prev);
-    hipSetDevice(S->device);
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(S->device);
     for (auto& sl : S->slots) {
         lookahead_destroy(&sl.la);
-        if (sl.s) hipStreamDestroy(sl.s);
+        if (sl.s) (void)hipStreamDestroy(sl.s);
     }
-    hipSetDevice(prev);
+    (void)hipSetDevice(prev);
     delete S;
     return MXP_OK;
 }
