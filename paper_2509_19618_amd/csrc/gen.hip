@@ -134,35 +134,66 @@ hipError_t generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void* A, 
 // Partial products P[c][r][i] = sum over the columns j of chunk c, j != i,
 // of A[i,j] * X[j,r], with A[i,j] regenerated.  A thread owns one row; all
 // threads of a wave walk the same columns, so X[j,r] is a wave-uniform load.
-template <int NR>
-__global__ __launch_bounds__(256) void k_regen_gemv(int64_t n, uint64_t seed, const double* __restrict__ X, int64_t ldx,
-                                                    double* __restrict__ P, int64_t chunk_cols) {
-    uint32_t k0[10], k1[10];
-    philox_keys(seed, k0, k1);
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    int64_t j0 = (int64_t)blockIdx.y * chunk_cols;
-    int64_t j1 = j0 + chunk_cols < n ? j0 + chunk_cols : n;
-    double acc[NR];
-#pragma unroll
-    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
-    uint32_t row = (uint32_t)(i < n ? i : 0);
-    for (int64_t j = j0; j < j1; j += 4) {
+// The sums are taken over the integer draws s (A[i,j] = s 2^-32) and scaled
+// by 2^-32 once at the end: scaling by a power of two commutes with every
+// rounding, so the result is that of summing the draws' values.  The sign
+// flip of the draws (s = word ^ 2^31) is folded into the last round keys for
+// words 0 and 2, which leave the last round xor-ed with them (the caller
+// passes those keys flipped); words 1 and 3 are flipped here.  Chunks start
+// at multiples of four columns; full quads of columns run without bound
+// checks, and the diagonal test is compiled in only for the work-groups
+// whose rows meet the chunk's columns.
+template <int NR, bool DIAG>
+MXP_DEV void regen_cols(uint32_t row, int64_t i, int64_t j0, int64_t j1, const uint32_t k0[10],
+                        const uint32_t k1[10], const double* __restrict__ X, int64_t ldx, double acc[NR]) {
+    const int64_t jq = j0 + ((j1 - j0) & ~(int64_t)3);
+    for (int64_t j = j0; j < jq; j += 4) {
         uint32_t w[4];
         philox4(row, (uint32_t)(j >> 2), 0u, k0, k1, w);
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
-            int64_t jj = j + t;
+            double a = (double)(int32_t)(w[t] ^ ((t & 1) ? 0x80000000u : 0u));
+            if (DIAG) a = ((uint32_t)(j + t) == (uint32_t)i) ? 0.0 : a;
+#pragma unroll
+            for (int r = 0; r < NR; ++r) acc[r] = fma(a, X[j + t + r * ldx], acc[r]);
+        }
+    }
+    if (jq < j1) {
+        uint32_t w[4];
+        philox4(row, (uint32_t)(jq >> 2), 0u, k0, k1, w);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int64_t jj = jq + t;
             if (jj < j1) {
-                double a = (double)draw_offset(w[t]) * 0x1p-32;
+                double a = (double)(int32_t)(w[t] ^ ((t & 1) ? 0x80000000u : 0u));
                 a = (jj == i) ? 0.0 : a;
 #pragma unroll
                 for (int r = 0; r < NR; ++r) acc[r] = fma(a, X[jj + r * ldx], acc[r]);
             }
         }
     }
+}
+
+template <int NR>
+__global__ __launch_bounds__(256) void k_regen_gemv(int64_t n, uint64_t seed, const double* __restrict__ X, int64_t ldx,
+                                                    double* __restrict__ P, int64_t chunk_cols) {
+    uint32_t k0[10], k1[10];
+    philox_keys(seed, k0, k1);
+    k0[9] ^= 0x80000000u;                     // sign flip of words 0 and 2
+    k1[9] ^= 0x80000000u;
+    const int64_t r_lo = (int64_t)blockIdx.x * 256;
+    const int64_t i = r_lo + threadIdx.x;
+    const int64_t j0 = (int64_t)blockIdx.y * chunk_cols;
+    const int64_t j1 = j0 + chunk_cols < n ? j0 + chunk_cols : n;
+    double acc[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) acc[r] = 0.0;
+    const uint32_t row = (uint32_t)(i < n ? i : 0);
+    if (r_lo < j1 && j0 < r_lo + 256) regen_cols<NR, true>(row, i, j0, j1, k0, k1, X, ldx, acc);
+    else regen_cols<NR, false>(row, i, j0, j1, k0, k1, X, ldx, acc);
     if (i < n) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) P[((int64_t)blockIdx.y * NR + r) * n + i] = acc[r];
+        for (int r = 0; r < NR; ++r) P[((int64_t)blockIdx.y * NR + r) * n + i] = acc[r] * 0x1p-32;
     }
 }
 

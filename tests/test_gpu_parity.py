@@ -55,7 +55,7 @@ def test_generator_regen_only_and_large_seed():
     assert np.array_equal(prob.diag.cpu().numpy(), d)
 
 
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (257, 1), (1000, 3), (2048, 8)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (257, 1), (770, 2), (1000, 3), (1027, 1), (2048, 8)])
 def test_residual_regen(n, nrhs):
     print("residual", n, nrhs, flush=True)
     prob = mxp.mxp_generate(n, nrhs, seed=7, store="f16", with_matrix=False)
