@@ -73,6 +73,26 @@ def test_residual_regen(n, nrhs):
         assert np.all(np.abs(AX[r] - A @ X[r]) <= bound + 1e-300)
 
 
+def test_residual_regen_chunks_meet_row_tiles_in_part():
+    # n = 20001: column chunks of 832 columns, not a multiple of the 256-row
+    # work-group tiles, so some work-groups' rows meet a chunk's columns (and
+    # the diagonal) in part; the last chunk has 33 columns (a ragged quad)
+    n, seed = 20001, 11
+    print("residual, partial chunk overlaps", n, flush=True)
+    prob = mxp.mxp_generate(n, 1, seed=seed, store="f16", with_matrix=False)
+    rng = np.random.default_rng(5)
+    x = rng.uniform(-1, 1, n)
+    b = prob.B[0].cpu().numpy()
+    R = mxp.mxp_residual(prob, torch.from_numpy(x[None, :]).cuda(), prob.B[:1])[0].cpu().numpy()
+    edges = [0, 255, 256, 767, 768, 800, 831, 832, 1023, 1024, 1663, 1664, 19967, 19968, 20000]
+    rows = np.unique(np.concatenate([edges, rng.choice(n, 64, replace=False)])).astype(np.int64)
+    want = oracle.residual_rows(n, seed, x, b, rows)
+    d = prob.diag.cpu().numpy()[rows]
+    # sum_j |A_ij| <= 2 A_ii; both sides are FP64 sums of n products
+    scale = 2.0 * d * np.abs(x).max() + np.abs(b[rows])
+    assert np.all(np.abs(R[rows] - want) <= 2 * n * 2.0 ** -53 * scale)
+
+
 CASES = [
     # n, nb, update, store, u_low bound factor
     (256, 64, "f32", "f32"),
