@@ -38,6 +38,7 @@ PEAK = {  # MI355X published dense peaks
     "bf16_tflops": 2500.0,
     "f8_tflops": 5000.0,
     "f32_tflops": 157.3,
+    "f64_tflops": 78.6,
 }
 
 
@@ -67,6 +68,10 @@ def parse():
                     help="only the serving stream, full protocol (2000 requests at 0.5x and 0.8x saturation)")
     ap.add_argument("--no-serving", action="store_true", help="leave the serving summary out of the default line")
     ap.add_argument("--serve-slots", type=int, default=8)
+    ap.add_argument("--no-configs", action="store_true", help="leave the other configurations out of the line")
+    ap.add_argument("--no-studies", action="store_true", help="leave the reduced kind and pivoting studies out")
+    ap.add_argument("--study", choices=["kinds", "pivoting"],
+                    help="only one study at its full sizes (matrix kinds x update precision; FP64 pivoting)")
     return ap.parse_args()
 
 
@@ -87,7 +92,8 @@ def serving_stream(torch, mxp, n_requests: int, drop: int, loads, sat_requests: 
     arena = int(1.25 * slots * mxp.server_request_bytes(16384, 8, 512))
     srv = mxp.Server(arena, max_slots=slots, update="bf16", store="bf16", autotune=True)
     try:
-        tuned = {n: srv.block_size(n) for n in (512, 1024, 2048, 4096, 8192, 16384)}
+        tuned = {n: {"nb": srv.block_size(n), "tile": "128x128" if srv.tile(n) == mxp.TILE_128x128 else "256x128"}
+                 for n in (512, 1024, 2048, 4096, 8192, 16384)}
         sat = draw(sat_requests)
         t0 = time.perf_counter()
         ids = [srv.submit(n, r, 1000 + k, want_x=False) for k, (n, r) in enumerate(sat)]
@@ -95,8 +101,12 @@ def serving_stream(torch, mxp, n_requests: int, drop: int, loads, sat_requests: 
         t_sat = time.perf_counter() - t0
         bad = sum(1 for i in ids if srv.wait(i).status != mxp.OK)
         rate_sat = len(sat) / t_sat
+        st = srv.stats()
         out = {"saturated_solves_per_s": round(rate_sat, 2), "saturation_requests": len(sat),
-               "saturation_failed": bad, "slots": slots, "tuned_nb": tuned, "runs": []}
+               "saturation_failed": bad, "slots": slots, "streams": st["streams"], "tuned": tuned,
+               "saturation_groups": st["groups"], "saturation_mean_group": round(st["grouped_requests"] /
+                                                                                 max(st["groups"], 1), 2),
+               "peak_group": st["peak_group"], "runs": []}
         for frac in loads:
             lam = frac * rate_sat
             reqs = draw(n_requests)
@@ -120,7 +130,8 @@ def serving_stream(torch, mxp, n_requests: int, drop: int, loads, sat_requests: 
                                 "p99_ms": round(float(np.percentile(lat, 99)), 3),
                                 "mean_ms": round(float(lat.mean()), 3), "all_valid": ok,
                                 "max_iters": max(x.iters for x in res), "max_eta": max(x.eta for x in res),
-                                "peak_in_flight": srv.stats()["peak_in_flight"]})
+                                "peak_in_flight": srv.stats()["peak_in_flight"],
+                                "peak_group": srv.stats()["peak_group"]})
         return out
     finally:
         srv.close()
@@ -215,31 +226,218 @@ def cpu_baseline(n: int, seed: int) -> dict:
                       "thread (OMP_NUM_THREADS=1), rate by the same 2/3 n^3 formula" % (n, seed, t)}
 
 
-def fp64_gpu_baseline(torch, mxp, n: int, seed: int) -> dict:
-    """FP64 LU solve with partial pivoting (torch -> rocSOLVER getrf/getrs) on
-    the same GPU and the exact FP64 matrix, timed the same way."""
+def fp64_gpu_baselines(torch, mxp, n: int, seed: int, reps: int = 3) -> dict:
+    """The FP64 solve on the same GPU and the exact FP64 matrix, timed the
+    same way as the mixed-precision solve (HIP events around factor + solve on
+    the current stream, one untimed warm-up, the mean of `reps` runs):
+      * own:       this library's FP64 LU without pivoting (FP64 matrix-core
+                   trailing update) and its FP64 triangular solves;
+      * rocsolver: torch.linalg.lu_factor_ex + lu_solve (rocSOLVER getrf /
+                   getrs, partial pivoting).
+      * own_rocblas: the same LU with rocBLAS dgemm as its trailing update.
+    The fastest one is the denominator of the speed-up."""
     prob = mxp.mxp_generate(n, 1, seed, store="f64")
+    A0 = prob.A.clone()
     A = mxp.as_matrix(prob.A, n)
     b = prob.B[0].clone().unsqueeze(1)
-    times = []
-    for it in range(3):
-        M = A.contiguous()
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        LU, piv, info = torch.linalg.lu_factor_ex(M)
-        x = torch.linalg.lu_solve(LU, piv, b)
-        e1.record()
-        torch.cuda.synchronize()
-        if it > 0:
-            times.append(e0.elapsed_time(e1))
-        del M, LU, piv
-    eta = mxp.mxp_hpl_eta(prob, x[:, 0].contiguous(), prob.B[0])
-    t = min(times)
-    del prob, A
+    work = torch.empty(mxp.lib().mxp_lu64_work_bytes(n), dtype=torch.uint8, device="cuda")
+    out = {}
+
+    def timed(fn):
+        times, x = [], None
+        for it in range(reps + 1):
+            prob.A.copy_(A0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            x = fn()
+            e1.record()
+            torch.cuda.synchronize()
+            if it > 0:
+                times.append(e0.elapsed_time(e1))
+        return statistics.mean(times), x
+
+    def own():
+        fac = mxp.mxp_lu64_factor(prob.A, n, prob.lda, pivot=False, sync_info=False, work=work)
+        return mxp.mxp_lu64_solve(fac, prob.B[:1])[0]
+
+    def own_rocblas():
+        fac = mxp.mxp_lu64_factor(prob.A, n, prob.lda, pivot=False, sync_info=False, work=work,
+                                  gemm=mxp.GEMM64_ROCBLAS)
+        return mxp.mxp_lu64_solve(fac, prob.B[:1])[0]
+
+    def rocsolver():
+        LU, piv, info = torch.linalg.lu_factor_ex(A.contiguous())
+        return torch.linalg.lu_solve(LU, piv, b)[:, 0]
+
+    mxp.profile_reset()
+    mxp.profile_enable(True, classes=[mxp.PROF_GEMM64])
+    t_own, x_own = timed(own)
+    mxp.profile_enable(False)
+    g = mxp.profile_read(mxp.PROF_GEMM64)
+    mxp.profile_reset()
+    mxp.profile_enable(True, classes=[mxp.PROF_GEMM64])
+    t_ob, x_ob = timed(own_rocblas)
+    mxp.profile_enable(False)
+    gb = mxp.profile_read(mxp.PROF_GEMM64)
+    t_roc, x_roc = timed(rocsolver)
+    for name, t, x, kind in (("own", t_own, x_own, "libmxp FP64 LU without pivoting (mxp_lu64_factor/solve)"),
+                             ("own_rocblas", t_ob, x_ob, "libmxp FP64 LU without pivoting, rocBLAS dgemm update"),
+                             ("rocsolver", t_roc, x_roc, "torch.linalg.lu_factor_ex + lu_solve, float64 "
+                                                         "(rocSOLVER getrf/getrs)")):
+        out[name] = {"value": (2.0 / 3.0) * n ** 3 / (t * 1e-3) / 1e12, "unit": "TFLOP/s", "ms": t,
+                     "eta": mxp.mxp_hpl_eta(prob, x.contiguous(), prob.B[0]), "kind": kind}
+    out["own"]["gemm64_tflops"] = g["flops"] / (g["ms"] * 1e-3) / 1e12 if g["ms"] > 0 else None
+    out["own"]["gemm64_frac_of_fp64_peak"] = (out["own"]["gemm64_tflops"] or 0.0) / PEAK["f64_tflops"]
+    out["own_rocblas"]["dgemm_tflops"] = gb["flops"] / (gb["ms"] * 1e-3) / 1e12 if gb["ms"] > 0 else None
+    best = max(("own", "own_rocblas", "rocsolver"), key=lambda k: out[k]["value"])
+    out["faster"] = best
+    del prob, A, A0, work
     torch.cuda.empty_cache()
-    return {"value": (2.0 / 3.0) * n ** 3 / (t * 1e-3) / 1e12, "unit": "TFLOP/s", "ms": t, "eta": eta,
-            "kind": "torch.linalg.lu_factor_ex + lu_solve, float64 (rocSOLVER getrf/getrs)"}
+    return out
+
+
+CONFIGS = [
+    # (name, n, nb, update, store, scaling, warmup, steps)
+    ("plain method, FP32 LU", 2048, 256, "f32", "f32", "none", 2, 5),
+    ("n=131072 BF16, unscaled", 131072, 1024, "bf16", "bf16", "none", 1, 1),
+    ("n=131072 BF16, row-equilibrated", 131072, 1024, "bf16", "bf16", "row_equil", 1, 1),
+    ("n=131072 FP16, unscaled", 131072, 1024, "f16", "f16", "none", 1, 1),
+    ("n=131072 FP16, row-equilibrated", 131072, 1024, "f16", "f16", "row_equil", 1, 1),
+    ("n=65536 FP8-E4M3, per-strip scales", 65536, 512, "f8", "f16", "none", 1, 2),
+    ("n=65536 FP16 (for the FP8 ratio)", 65536, 512, "f16", "f16", "none", 1, 2),
+]
+
+
+def config_runs(torch, mxp, seed: int) -> list:
+    """The other configurations, each timed like the headline (inputs
+    generated once and restored before every step, untimed; scaling, LU and
+    refinement timed), with the trailing update's own rate from HIP events."""
+    out = []
+    L = mxp.lib()
+    cache = {}
+    for name, n, nb, update, store, scaling, warmup, steps in CONFIGS:
+        key = (n, store)
+        if key not in cache:
+            cache.clear()
+            torch.cuda.empty_cache()
+            prob = mxp.mxp_generate(n, 1, seed, store=store)
+            cache[key] = (prob, prob.A.clone())
+        prob, A0 = cache[key]
+        up = mxp.dtype_code(update)
+        aux = torch.empty(L.mxp_factor_aux_bytes(n, nb), dtype=torch.uint8, device="cuda")
+        fwork = torch.empty(L.mxp_factor_work_bytes(n, nb, up), dtype=torch.uint8, device="cuda")
+        swork = torch.empty(L.mxp_solve_work_bytes(n, 1, 30), dtype=torch.uint8, device="cuda")
+        X = torch.empty((1, n), dtype=torch.float64, device="cuda")
+        stream = torch.cuda.current_stream()
+        sc = mxp.SCALE_ROW_EQUIL if scaling == "row_equil" else mxp.SCALE_NONE
+        times, res = [], None
+        for it in range(warmup + steps):
+            prob.A.copy_(A0)
+            timed = it >= warmup
+            if timed:
+                mxp.profile_reset()
+                mxp.profile_enable(True, classes=[mxp.PROF_GEMM])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            fac = mxp.mxp_factor(prob, nb, update, work=fwork, aux=aux, scaling=sc)
+            res = mxp.mxp_solve_ir(prob, fac, work=swork, X=X)
+            if timed:
+                e1.record(stream)
+                torch.cuda.synchronize()
+                mxp.profile_enable(False)
+                times.append(e0.elapsed_time(e1))
+                g = mxp.profile_read(mxp.PROF_GEMM)
+        ms = statistics.mean(times)
+        tflops_upd = g["flops"] / (g["ms"] * 1e-3) / 1e12
+        peak = PEAK["%s_tflops" % update]
+        intensity = g["flops"] / g["bytes"]
+        ridge = peak * 1e12 / (PEAK["hbm_gbs"] * 1e9)
+        if intensity >= ridge:
+            roof = {"bound": "mfma", "achieved": round(tflops_upd, 1), "peak": peak, "unit": "TFLOP/s",
+                    "frac": round(tflops_upd / peak, 4)}
+        else:
+            gbs = g["bytes"] / (g["ms"] * 1e-3) / 1e9
+            roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK["hbm_gbs"], "unit": "GB/s",
+                    "frac": round(gbs / PEAK["hbm_gbs"], 4)}
+        roof.update({"kernel": "k_gemm_update<%s,%s>" % (update, store), "mfma_tflops": round(tflops_upd, 1),
+                     "mfma_frac": round(tflops_upd / peak, 4), "launches": g["launches"]})
+        out.append({"config": name, "n": n, "nb": nb, "update": update, "store": store, "scaling": scaling,
+                    "value": round((2.0 / 3.0) * n ** 3 / (ms * 1e-3) / 1e12, 2), "unit": "TFLOP/s",
+                    "ms": round(ms, 3), "steps": steps, "iters": res.iters[0], "eta": res.eta[0],
+                    "valid": res.status[0] == 0 and res.eta[0] < 16, "update_roofline": roof})
+        print(json.dumps({"config_done": name, "ms": round(ms, 3)}), file=sys.stderr, flush=True)
+        del aux, fwork, swork, X, fac, res
+    cache.clear()
+    torch.cuda.empty_cache()
+    return out
+
+
+def kinds_study(torch, mxp, n: int, nb: int, seed: int) -> list:
+    """Iterations and backward error of the low-precision LU + GMRES-IR
+    against the diagonal of the matrix ("Matrix Generation": the dominant
+    diagonal is for debugging; a diagonal gamma sqrt(n) departs from
+    dominance, and near gamma = 1/sqrt(12) leaves GMRES without a
+    preconditioner far from convergence) and the update precision."""
+    out = []
+    for kind, gamma in ((mxp.GEN_DOMINANT, 0.0), (mxp.GEN_SQRTN, 1.0), (mxp.GEN_SQRTN, 0.5), (mxp.GEN_SQRTN, 0.3)):
+        for update, store in (("f16", "f16"), ("bf16", "bf16"), ("f8", "f16")):
+            prob = mxp.mxp_generate(n, 1, seed, store=store, kind=kind, gamma=gamma)
+            A0 = prob.A.clone()
+            rec = {"kind": {mxp.GEN_DOMINANT: "dominant", mxp.GEN_SQRTN: "sqrt(n)"}[kind], "gamma": gamma,
+                   "update": update, "store": store, "n": n, "nb": nb}
+            for rep in range(2):                                   # the first run warms up
+                prob.A.copy_(A0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fac = mxp.mxp_factor(prob, nb, update)
+                if fac.info:
+                    rec.update({"status": "singular pivot", "info": fac.info})
+                    break
+                res = mxp.mxp_solve_ir(prob, fac)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                rec.update({"iters": res.iters[0], "eta": res.eta[0], "status": res.status[0], "ms": round(1e3 * t, 2),
+                            "tflops": round((2.0 / 3.0) * n ** 3 / t / 1e12, 2)})
+            out.append(rec)
+            del prob, A0
+            torch.cuda.empty_cache()
+    return out
+
+
+def pivot_study(torch, mxp, sizes, seeds) -> list:
+    """The FP64 experiments behind Figures 2-4 ("Experimental Results"):
+    entries uniform in [-1, 1) without diagonal scaling, LU in FP64 with and
+    without partial pivoting; the largest pivot |u_kk| of the pivoted LU and
+    where it falls, next to sqrt(n), 5/8 sqrt(n) and n^0.45; the 1-, 2- and
+    inf-norms of the residual b - A x of both solves (and the HPL scaled
+    residual of each)."""
+    out = []
+    for n in sizes:
+        for seed in seeds:
+            rec = {"n": n, "seed": seed, "sqrt_n": n ** 0.5, "five_eighths_sqrt_n": 0.625 * n ** 0.5,
+                   "n_pow_045": n ** 0.45}
+            prob = mxp.mxp_generate(n, 1, seed, store="f64", kind=mxp.GEN_UNIFORM)
+            A0 = prob.A.clone()
+            for pivot in (True, False):
+                prob.A.copy_(A0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                fac = mxp.mxp_lu64_factor(prob.A, n, prob.lda, pivot=pivot)
+                x = mxp.mxp_lu64_solve(fac, prob.B[:1])
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                r = mxp.mxp_residual(prob, x, prob.B[:1])[0]
+                d = mxp.as_matrix(prob.A, n).diagonal().abs()
+                key = "pivoting" if pivot else "no_pivoting"
+                rec[key] = {"r_1": float(r.abs().sum()), "r_2": float(r.norm()), "r_inf": float(r.abs().max()),
+                            "eta": mxp.mxp_hpl_eta(prob, x[0].contiguous(), prob.B[0]), "info": fac.info,
+                            "ms": round(1e3 * t, 2), "max_pivot": float(d.max()),
+                            "max_pivot_at_frac": round(float(d.argmax()) / n, 4)}
+            out.append(rec)
+            del prob, A0
+            torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -255,6 +453,14 @@ def main():
     import torch
     import paper_2509_19618_amd as mxp
 
+    if args.study == "kinds":
+        print(json.dumps({"study": "kinds", "runs": kinds_study(torch, mxp, 32768, 512, args.seed)}), flush=True)
+        return
+    if args.study == "pivoting":
+        print(json.dumps({"study": "pivoting",
+                          "runs": pivot_study(torch, mxp, (1000, 2000, 4000, 8000, 16000, 32000, 46340), (1, 2, 3))}),
+              flush=True)
+        return
     if args.serve:
         sv = serving_stream(torch, mxp, 2000, 200, (0.5, 0.8), 400, args.serve_slots)
         r8 = sv["runs"][-1]
@@ -387,15 +593,21 @@ def main():
     prob = None
     torch.cuda.empty_cache()
     if not args.no_serving:
-        sv = serving_stream(torch, mxp, 600, 60, (0.8,), 200, args.serve_slots)
+        sv = serving_stream(torch, mxp, 600, 60, (0.5, 0.8), 200, args.serve_slots)
         r8 = sv["runs"][-1]
         line["p50_ms_served"] = r8["p50_ms"]
         line["p99_ms_served"] = r8["p99_ms"]
         line["serving"] = sv
+    if not args.no_configs:
+        line["configs"] = config_runs(torch, mxp, args.seed)
+    if not args.no_studies:
+        line["study_kinds"] = kinds_study(torch, mxp, 16384, 512, args.seed)
+        line["study_pivoting"] = pivot_study(torch, mxp, (2000, 8000, 32000), (1,))
     if not args.no_fp64_baseline:
-        fb = fp64_gpu_baseline(torch, mxp, n, args.seed)
-        line["fp64_baseline"] = {k: (round(v, 3) if isinstance(v, float) else v) for k, v in fb.items()}
-        line["speedup_vs_fp64_lu"] = round(value / fb["value"], 2)
+        fb = fp64_gpu_baselines(torch, mxp, n, args.seed)
+        line["fp64_baseline"] = {k: ({kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                                     if isinstance(v, dict) else v) for k, v in fb.items()}
+        line["speedup_vs_fp64_lu"] = round(value / fb[fb["faster"]]["value"], 2)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, args.seed)
         line["cpu_baseline"]["value"] = round(line["cpu_baseline"]["value"], 6)

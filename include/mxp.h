@@ -78,25 +78,44 @@ const char *mxp_last_error(void);
 /* library version string */
 const char *mxp_version(void);
 
+/* matrix kinds of mxp_generate ("Matrix Generation"; "Experimental Results") */
+enum {
+    MXP_GEN_DOMINANT = 0,  /* off-diagonal uniform in [-1/2, 1/2), diagonal = sum of |row|: the
+                              diagonally dominant class meant for debugging and tuning */
+    MXP_GEN_SQRTN = 1,     /* off-diagonal as above, diagonal = own draw + gamma sqrt(n): the
+                              sqrt(n) scaling suggested by random-matrix theory; far from row
+                              dominance, and for gamma near 1/sqrt(12) hard for GMRES
+                              without a preconditioner */
+    MXP_GEN_UNIFORM = 2    /* every entry uniform in [-1, 1), no diagonal scaling: the matrices
+                              of the pivoting experiments (Figures 2-4) */
+};
+
 /*
  * mxp_generate -- "Matrix Generation".
- * Generates A (n x n) and B (n x nrhs) from `seed`:
- *   A[i,j] = k(i,j) * 2^-32 - 1/2 for i != j, with k the 32-bit Philox4x32-10
- *            draw of stream 0 at counter (i, j/4, 0, 0), word j%4, key =
- *            (seed low 32 bits, seed high 32 bits);
- *   A[i,i] = sum over ALL j of |k(i,j) * 2^-32 - 1/2| (computed exactly);
- *   B[i,r] = draw of stream 1 at (i, r) mapped the same way.
+ * Generates A (n x n) and B (n x nrhs) from `seed`.  With k(i,j) the 32-bit
+ * Philox4x32-10 draw of stream 0 at counter (i, j/4, 0, 0), word j%4, key =
+ * (seed low 32 bits, seed high 32 bits), and u(i,j) = k(i,j) 2^-32 - 1/2:
+ *   MXP_GEN_DOMINANT: A[i,j] = u(i,j) (i != j),
+ *                     A[i,i] = sum over ALL j of |u(i,j)| (exact);
+ *   MXP_GEN_SQRTN:    A[i,j] = u(i,j) (i != j),
+ *                     A[i,i] = u(i,i) + fl(gamma * fl(sqrt(n))) (one FP64 add);
+ *   MXP_GEN_UNIFORM:  A[i,j] = 2 u(i,j) for every i, j.
+ *   B[i,r] = draw of stream 1 at (i, r) mapped to [-1/2, 1/2) the same way.
  * A is written in the storage format `store` (MXP_F32, MXP_F16, MXP_BF16, or
  * MXP_F64 for an exact copy), each entry rounded to nearest even from its
  * exact value; lda >= n.
  * A may be NULL (nothing stored: the solver regenerates A on the fly).
  * B (FP64, ldb >= n) may be NULL when nrhs == 0.
- * diag (FP64, n entries): the exact diagonal; required.
- * a_inf (FP64, 1 entry): ||A||_inf of the exact matrix; required.
+ * gamma: the diagonal coefficient of MXP_GEN_SQRTN (> 0), ignored otherwise.
+ * diag (FP64, n entries): the exact diagonal (the regenerating residual
+ *   reads it); required.
+ * row_l1 (FP64, n entries, may be NULL): ||A[i,:]||_1 of the exact matrix
+ *   (exact for the dominant and uniform kinds; one rounding for sqrt(n)).
+ * a_inf (FP64, 1 entry): ||A||_inf = max_i row_l1[i]; required.
  * Asynchronous on `stream`.  n >= 1, n < 2^31.
  */
-int mxp_generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void *A, int64_t lda,
-                 double *B, int64_t ldb, double *diag, double *a_inf, void *stream);
+int mxp_generate(int64_t n, int64_t nrhs, uint64_t seed, int kind, double gamma, int store, void *A, int64_t lda,
+                 double *B, int64_t ldb, double *diag, double *row_l1, double *a_inf, void *stream);
 
 /*
  * Factorisation -- "Algorithmic Framework", Figure 1.
@@ -129,12 +148,75 @@ int mxp_generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void *A, int
  * `info` (host pointer, may be NULL): if non-NULL the call synchronises
  * the stream and stores 0 or the 1-based column of the first zero /
  * non-finite pivot, returning MXP_ESINGULAR in the latter case; if NULL
- * the call is asynchronous and a singular pivot is not reported.
+ * the call is asynchronous and a singular pivot is NOT reported -- an
+ * asynchronous caller that needs the report reads the info word of `work`
+ * (mxp_factor_get_layout: work offset `info`, an unsigned 64-bit value, all
+ * ones when no pivot failed) after the stream has finished.
+ * Concurrency: the factorisation runs on `stream` and on a side stream of
+ * its own (look-ahead); each call takes a side stream and its events from a
+ * per-device pool for the time of the call, so host threads may factor at
+ * the same time on different streams.  Calls sharing `work`, `aux` or `A`
+ * must be ordered by the caller.
  */
 size_t mxp_factor_aux_bytes(int64_t n, int64_t nb);
 size_t mxp_factor_work_bytes(int64_t n, int64_t nb, int update);
 int mxp_factor(int64_t n, int64_t nb, int update, int store, int scaling, const double *diag, void *A,
                int64_t lda, void *aux, void *work, size_t work_bytes, int64_t *info, void *stream);
+
+/*
+ * mxp_factor_group -- the factorisations of up to 8 independent matrices of
+ * the same formats in lockstep on one stream (the batched launches of the
+ * solve server; not in the paper): per block step ONE launch factors the
+ * diagonal blocks of all of them, ONE launch forms all their strip TRSMs
+ * and ONE launch updates all their trailing matrices, each kernel finding
+ * its matrix through a descriptor array.  Sizes and block sizes may differ;
+ * no look-ahead.  Each item's A, aux and work are as for mxp_factor (no
+ * scaling); the results are those of mxp_factor bit for bit.
+ * tile: the work-group tile of the trailing update, MXP_TILE_256x128 (the
+ *   one mxp_factor uses) or MXP_TILE_128x128 (twice the tiles: small n).
+ * info: host array of count entries (may be NULL: asynchronous), as for
+ *   mxp_factor; MXP_ESINGULAR if any matrix had a bad pivot.
+ */
+enum { MXP_TILE_256x128 = 0, MXP_TILE_128x128 = 1 };
+typedef struct {
+    int64_t n, nb;
+    void *A;
+    int64_t lda;
+    void *aux, *work;
+    size_t work_bytes;
+} mxp_factor_item;
+int mxp_factor_group(int count, const mxp_factor_item *items, int update, int store, int tile, int64_t *info,
+                     void *stream);
+
+/*
+ * Where mxp_factor puts things in `aux` and `work` (byte offsets), for
+ * inspection and testing.  With nblk = ceil(n / nb) diagonal blocks and
+ * strips = ceil(n / 32):
+ *   aux:  T         FP32 nblk x nb x nb: L11\U11 of every diagonal block
+ *                   (column-major, ld nb; the FP32 factor the preconditioner
+ *                   applies)
+ *         Trm       the same, row-major
+ *         linv/uinv FP32 nblk x (nb/64) x 64 x 64: inverses of the 64 x 64
+ *                   diagonal sub-blocks (L column-major, U row-major)
+ *         lsc       FP32 nblk x strips: the power-of-two factor s of every
+ *                   stored 32-row strip of L21 (entry [blk][r/32]; the
+ *                   stored value is s * L), 1 where no scaling is applied
+ *         rowscale  FP64 n: the row scaling S (1 without equilibration)
+ *         linv_full/uinv_full FP32 nblk x nb x nb: L11^-1 and U11^-1
+ *   work: Lq/Uq     two alternating sets of op_rows x nb update operands
+ *                   (row-major: K contiguous), set (k/nb) & 1 for step k;
+ *                   row 0 of a set is the first row after the step's block
+ *         inv_sa/inv_sb two sets of op_rows/32 FP32 factors 1/s per
+ *                   32-row strip of Lq / Uq
+ *         info      unsigned 64-bit: first failing pivot column, ~0 if none
+ * Returns MXP_EINVAL for sizes mxp_factor would reject.
+ */
+typedef struct {
+    size_t T, Trm, linv, uinv, lsc, rowscale, linv_full, uinv_full, aux_bytes;
+    size_t Lq, Uq, inv_sa, inv_sb, info, work_bytes;
+    int64_t op_rows, strips;
+} mxp_factor_layout;
+int mxp_factor_get_layout(int64_t n, int64_t nb, int update, mxp_factor_layout *out);
 
 /* per-right-hand-side outcome of the refinement */
 typedef struct {
@@ -158,8 +240,8 @@ typedef struct {
  * All vector work runs in FP64 on the device; only the convergence scalars
  * cross to the host.
  *
- * LU/lda/aux/nb/update/store: as produced by mxp_factor.  seed, diag and
- * a_inf: as given to / produced by mxp_generate.  B (ldb >= n) is read,
+ * LU/lda/aux/nb/update/store: as produced by mxp_factor.  seed, kind, diag
+ * and a_inf: as given to / produced by mxp_generate.  B (ldb >= n) is read,
  * X (ldx >= n) written.  rep: host array of nrhs reports.
  * restart in [1, 64]; max_iters >= 1; tol > 0 (16 for the HPL test);
  * tau >= 0 (2^-50 recommended).
@@ -167,7 +249,7 @@ typedef struct {
  * when every right-hand side passed, else the worst positive status.
  */
 size_t mxp_solve_work_bytes(int64_t n, int64_t nrhs, int restart);
-int mxp_solve_ir(int64_t n, int64_t nb, int update, int store, uint64_t seed, const void *LU, int64_t lda,
+int mxp_solve_ir(int64_t n, int64_t nb, int update, int store, uint64_t seed, int kind, const void *LU, int64_t lda,
                  const void *aux, const double *diag, const double *a_inf, const double *B, int64_t ldb,
                  double *X, int64_t ldx, int64_t nrhs, int restart, int max_iters, double tol, double tau,
                  mxp_rhs_report *rep, void *work, size_t work_bytes, void *stream);
@@ -177,7 +259,7 @@ int mxp_solve_ir(int64_t n, int64_t nb, int update, int store, uint64_t seed, co
  * each has a *_work_bytes query for its scratch buffer).
  *
  * mxp_residual: R = B - A X for nrhs columns (R = A X when B is NULL),
- *   FP64, A regenerated from (seed, diag) -- the refinement's residual
+ *   FP64, A regenerated from (seed, kind, diag) -- the refinement's residual
  *   ("Algorithmic Framework": the 64-bit residual of the refinement).
  * mxp_apply_prec: Z = M^-1 V = U^-1 L^-1 S V for nrhs columns (nrhs <= 64),
  *   FP64 arithmetic on the stored factor (the left preconditioner);
@@ -187,8 +269,9 @@ int mxp_solve_ir(int64_t n, int64_t nb, int update, int store, uint64_t seed, co
  *   device) written to the host double *eta; synchronises.
  */
 size_t mxp_residual_work_bytes(int64_t n, int64_t nrhs);
-int mxp_residual(int64_t n, uint64_t seed, const double *diag, const double *X, int64_t ldx, const double *B,
-                 int64_t ldb, double *R, int64_t ldr, int64_t nrhs, void *work, size_t work_bytes, void *stream);
+int mxp_residual(int64_t n, uint64_t seed, int kind, const double *diag, const double *X, int64_t ldx,
+                 const double *B, int64_t ldb, double *R, int64_t ldr, int64_t nrhs, void *work, size_t work_bytes,
+                 void *stream);
 size_t mxp_apply_prec_work_bytes(int64_t n, int64_t nrhs);
 int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, const void *LU, int64_t lda, const void *aux,
                    const double *V, int64_t ldv, double *Z, int64_t ldz, int64_t nrhs, void *work, size_t work_bytes,
@@ -206,14 +289,47 @@ int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, const void *LU,
 int mxp_trailing_update(int64_t M, int64_t N, int64_t K, int update, int store, void *C, int64_t ldc,
                         const void *Aq, const void *Bq, const float *inv_sa, const float *inv_sb, void *stream);
 size_t mxp_hpl_eta_work_bytes(int64_t n);
-int mxp_hpl_eta(int64_t n, uint64_t seed, const double *diag, const double *a_inf, const double *x,
+int mxp_hpl_eta(int64_t n, uint64_t seed, int kind, const double *diag, const double *a_inf, const double *x,
                 const double *b, double *eta, void *work, size_t work_bytes, void *stream);
+
+/*
+ * FP64 LU -- the FP64 solve the figure of merit is compared with
+ * ("Background"), and the LU of the pivoting study ("Experimental Results",
+ * Figures 2-4: LU in 64-bit arithmetic with and without partial pivoting).
+ * Right-looking blocked LU of the FP64 matrix A (n x n, lda >= n, in place:
+ * L unit lower and U), block size 128 (64 above n = 32768), trailing update
+ * on the FP64 matrix cores.
+ * ipiv (device, n int64 entries, may be NULL): NULL factors without
+ *   pivoting; otherwise partial pivoting (largest magnitude in the column,
+ *   the first among equals, as LAPACK getrf) with ipiv[k] = the 0-based row
+ *   swapped with row k; the swaps are applied to the whole matrix.
+ *   Pivoting needs n <= 65536.
+ * gemm: the trailing update, MXP_GEMM64_OWN (this library's FP64 matrix-core
+ *   kernel, mxp_trailing_update64) or MXP_GEMM64_ROCBLAS (rocBLAS dgemm, a
+ *   plain library GEMM: the baseline at the vendor library's speed).
+ * work: mxp_lu64_work_bytes(n) bytes of device scratch.
+ * info (host, may be NULL): as mxp_factor (synchronises, MXP_ESINGULAR and
+ *   the 1-based column of the first zero / non-finite pivot); MXP_EHIP if a
+ *   bounded wait of the pivoted panel expired.  NULL: asynchronous.
+ * mxp_lu64_solve: X <- U^-1 L^-1 P X for nrhs <= 64 columns (ldx >= n), with
+ *   the factors and ipiv (may be NULL) of mxp_lu64_factor.  Asynchronous.
+ */
+enum { MXP_GEMM64_OWN = 0, MXP_GEMM64_ROCBLAS = 1 };
+size_t mxp_lu64_work_bytes(int64_t n);
+/* the FP64 trailing update C (M x N, ldc) -= A (M x K, lda) B (K x N, ldb),
+ * column-major, K a multiple of 4, on the FP64 matrix cores; asynchronous */
+int mxp_trailing_update64(int64_t M, int64_t N, int64_t K, double *C, int64_t ldc, const double *A, int64_t lda,
+                          const double *B, int64_t ldb, void *stream);
+int mxp_lu64_factor(int64_t n, double *A, int64_t lda, int64_t *ipiv, int gemm, void *work, size_t work_bytes,
+                    int64_t *info, void *stream);
+int mxp_lu64_solve(int64_t n, const double *LU, int64_t lda, const int64_t *ipiv, double *X, int64_t ldx,
+                   int64_t nrhs, void *stream);
 
 /*
  * Timing of kernel classes with HIP events recorded on the stream each
  * kernel is launched on (off by default).  Classes: 0 trailing update,
  * 1 strip TRSMs, 2 diagonal-block LU, 3 preconditioner apply, 4 regenerating
- * residual / matrix-vector product.  mxp_profile_enable(mask) times the
+ * residual / matrix-vector product, 6 FP64 trailing update (mxp_lu64_*).  mxp_profile_enable(mask) times the
  * classes whose bit is set in mask (0: timing off); the events add work to
  * each timed launch's stream.  mxp_profile_read synchronises on the
  * recorded events and returns, for one class, the summed kernel time, the
@@ -227,16 +343,21 @@ int mxp_profile_read(int cls, double *total_ms, double *flops, double *bytes, in
 /*
  * ---------------------------------------------------------------- serving
  * A solve server on one device: requests (n, nrhs, seed) arrive at any
- * time; each is generated, factored and refined exactly as by mxp_generate +
- * mxp_factor + mxp_solve_ir.  Requests are admitted in arrival order as soon
- * as a slot is free and their device memory fits in the HBM budget (the
- * caller's arena, sub-allocated by the server); up to max_slots requests are
- * in flight at once, each on its own stream, so that the kernels of requests
- * at different stages overlap on the device (continuous batching).  The
- * block size of each request is chosen by size class; with `autotune` the
- * server times the candidate block sizes of every class on the device at
- * creation and keeps the fastest.  The paper has no serving part; the calls
- * follow its statement of the problem for every request.
+ * time; each is generated, factored and refined with the same arithmetic as
+ * mxp_generate + mxp_factor + mxp_solve_ir.  Requests are admitted in arrival
+ * order as soon as a slot is free and their device memory fits in the HBM
+ * budget (the caller's arena, sub-allocated by the server); up to max_slots
+ * requests are in flight at once.  A few worker threads (at most 3, one
+ * stream each) take groups of admitted requests: a group's factorisations
+ * run in lockstep with one launch per kernel and block step for the whole
+ * group (mxp_factor_group), then each request is refined with all its
+ * right-hand sides together and returned; requests that arrive meanwhile
+ * form the next groups, which overlap on the device (continuous batching).
+ * The block size and trailing-update tile of each request are chosen by
+ * size class; with `autotune` the server times every candidate pair of each
+ * class on the device at creation and keeps the fastest.  The paper has no
+ * serving part; the calls follow its statement of the problem for every
+ * request.
  *
  * Ownership: `arena` is a device buffer of arena_bytes owned by the caller,
  * valid until mxp_server_destroy returns.  x_host given to submit is a host
@@ -272,6 +393,10 @@ typedef struct {
     int64_t submitted, completed, failed;
     int64_t in_flight, peak_in_flight;
     size_t arena_bytes, bytes_in_use, peak_bytes_in_use;
+    int64_t groups;            /* groups factored together (one launch per kernel and block step) */
+    int64_t grouped_requests;  /* requests in those groups */
+    int64_t peak_group;        /* largest group */
+    int64_t streams;           /* device streams of the server (one per worker) */
 } mxp_server_stats;
 
 /* device bytes one request needs (A, B, X, diag and all work spaces) */
@@ -299,6 +424,9 @@ int mxp_server_get_stats(mxp_server *srv, mxp_server_stats *out);
 
 /* block size the server uses for a request of size n */
 int64_t mxp_server_block_size(mxp_server *srv, int64_t n);
+
+/* trailing-update tile (MXP_TILE_*) the server uses for a request of size n */
+int mxp_server_tile(mxp_server *srv, int64_t n);
 
 /* drains, stops the slot threads and releases the server's streams */
 int mxp_server_destroy(mxp_server *srv);

@@ -32,6 +32,9 @@ _LIB = os.path.join(_HERE, "libmxp_oracle.so")
 
 FMT_F32, FMT_F16, FMT_BF16, FMT_E4M3 = 0, 1, 2, 3
 EPS = 2.0 ** -53
+# matrix kinds ("Matrix Generation"; "Experimental Results"): row-dominant
+# diagonal, diagonal u_ii + gamma sqrt(n), uniform in [-1, 1) without scaling
+GEN_DOMINANT, GEN_SQRTN, GEN_UNIFORM = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
@@ -52,27 +55,29 @@ def lib():
     if _lib is None:
         build()
         L = ctypes.CDLL(_LIB)
-        i64, u64, u32, dbl = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double
+        i64, u64, u32, dbl, ci = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_double, ctypes.c_int
         P = ctypes.c_void_p
         sig = {
             "orc_philox4x32_10": (None, [P, P, P]),
             "orc_draw": (u32, [u64, u32, i64, i64]),
             "orc_entry_draw": (dbl, [u64, i64, i64]),
             "orc_rhs": (dbl, [u64, i64, i64]),
-            "orc_diag": (dbl, [i64, u64, i64]),
-            "orc_entry": (dbl, [i64, u64, i64, i64]),
-            "orc_generate": (None, [i64, u64, P, i64, P]),
+            "orc_diag": (dbl, [i64, u64, ci, dbl, i64]),
+            "orc_entry": (dbl, [i64, u64, ci, dbl, i64, i64]),
+            "orc_generate": (None, [i64, u64, ci, dbl, P, i64, P, P]),
             "orc_generate_rhs": (None, [i64, i64, u64, P, i64]),
-            "orc_anorm_inf_regen": (dbl, [i64, u64]),
+            "orc_anorm_inf_regen": (dbl, [i64, u64, ci, dbl]),
             "orc_norm_inf_mat": (dbl, [i64, P, i64]),
             "orc_matvec": (None, [i64, P, i64, P, P]),
             "orc_lu_nopiv": (i64, [i64, P, i64]),
             "orc_lu_solve": (None, [i64, P, i64, P]),
+            "orc_lu_pp": (i64, [i64, P, i64, P]),
+            "orc_apply_pivots": (None, [i64, P, P]),
             "orc_hpl_eta": (dbl, [i64, P, i64, P, P]),
-            "orc_residual_regen": (None, [i64, u64, P, P, P]),
-            "orc_residual_rows": (None, [i64, u64, P, P, P, i64, P]),
-            "orc_hpl_eta_regen": (dbl, [i64, u64, P, P]),
-            "orc_jacobi_regen": (i64, [i64, u64, P, P, i64, dbl]),
+            "orc_residual_regen": (None, [i64, u64, ci, dbl, P, P, P]),
+            "orc_residual_rows": (None, [i64, u64, ci, dbl, P, P, P, i64, P]),
+            "orc_hpl_eta_regen": (dbl, [i64, u64, ci, dbl, P, P, dbl]),
+            "orc_jacobi_regen": (i64, [i64, u64, ci, dbl, P, P, i64, dbl]),
             "orc_gmres_cycle": (i64, [i64, P, i64, P, i64, P, P, i64, dbl, P, i64, P, P, P, P]),
             "orc_gmres_ir": (ctypes.c_int, [i64, P, i64, P, i64, P, P, i64, i64, dbl, dbl, P, P, P]),
             "orc_round_fmt": (dbl, [ctypes.c_int, dbl, ctypes.c_int]),
@@ -107,16 +112,18 @@ def draw(seed: int, stream: int, i: int, j: int) -> int:
     return int(lib().orc_draw(seed, stream, i, j))
 
 
-def entry(n: int, seed: int, i: int, j: int) -> float:
-    return float(lib().orc_entry(n, seed, i, j))
+def entry(n: int, seed: int, i: int, j: int, kind: int = GEN_DOMINANT, gamma: float = 0.0) -> float:
+    return float(lib().orc_entry(n, seed, kind, gamma, i, j))
 
 
-def generate(n: int, seed: int):
-    """Dense FP64 A (column-major, returned as a Fortran-ordered array) and diag."""
+def generate(n: int, seed: int, kind: int = GEN_DOMINANT, gamma: float = 0.0, row_l1: bool = False):
+    """Dense FP64 A (column-major, returned as a Fortran-ordered array) and
+    diag (and the row 1-norms when row_l1)."""
     A = np.zeros((n, n), dtype=np.float64, order="F")
     d = np.zeros(n, dtype=np.float64)
-    lib().orc_generate(n, seed, _p(A), n, _p(d))
-    return A, d
+    l1 = np.zeros(n, dtype=np.float64)
+    lib().orc_generate(n, seed, kind, gamma, _p(A), n, _p(d), _p(l1))
+    return (A, d, l1) if row_l1 else (A, d)
 
 
 def generate_rhs(n: int, nrhs: int, seed: int) -> np.ndarray:
@@ -125,8 +132,8 @@ def generate_rhs(n: int, nrhs: int, seed: int) -> np.ndarray:
     return B
 
 
-def anorm_inf_regen(n: int, seed: int) -> float:
-    return float(lib().orc_anorm_inf_regen(n, seed))
+def anorm_inf_regen(n: int, seed: int, kind: int = GEN_DOMINANT, gamma: float = 0.0) -> float:
+    return float(lib().orc_anorm_inf_regen(n, seed, kind, gamma))
 
 
 # ---------------------------------------------------------------- dense LA
@@ -136,6 +143,24 @@ def lu_nopiv(A: np.ndarray):
     n = LU.shape[0]
     info = lib().orc_lu_nopiv(n, _p(LU), n)
     return LU, int(info)
+
+
+def lu_pp(A: np.ndarray):
+    """LU with partial pivoting of a copy of A ("Experimental Results");
+    returns (LU packed, ipiv with 0-based swap rows, info)."""
+    LU = np.array(A, dtype=np.float64, order="F", copy=True)
+    n = LU.shape[0]
+    ipiv = np.zeros(n, dtype=np.int64)
+    info = lib().orc_lu_pp(n, _p(LU), n, ipiv.ctypes.data_as(ctypes.c_void_p))
+    return LU, ipiv, int(info)
+
+
+def lu_pp_solve(LU: np.ndarray, ipiv, b) -> np.ndarray:
+    """x = U^-1 L^-1 P b for the factors of lu_pp"""
+    x = _f64(b).copy()
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int64)
+    lib().orc_apply_pivots(LU.shape[0], ipiv.ctypes.data_as(ctypes.c_void_p), _p(x))
+    return lu_solve(LU, x)
 
 
 def lu_solve(LU: np.ndarray, b) -> np.ndarray:
@@ -158,28 +183,32 @@ def hpl_eta(A: np.ndarray, x, b) -> float:
     return float(lib().orc_hpl_eta(A.shape[0], _p(A), A.shape[0], _p(_f64(x)), _p(_f64(b))))
 
 
-def residual_regen(n: int, seed: int, x, b) -> np.ndarray:
+def residual_regen(n: int, seed: int, x, b, kind: int = GEN_DOMINANT, gamma: float = 0.0) -> np.ndarray:
     r = np.zeros(n)
-    lib().orc_residual_regen(n, seed, _p(_f64(x)), _p(_f64(b)), _p(r))
+    lib().orc_residual_regen(n, seed, kind, gamma, _p(_f64(x)), _p(_f64(b)), _p(r))
     return r
 
 
-def residual_rows(n: int, seed: int, x, b, rows) -> np.ndarray:
+def residual_rows(n: int, seed: int, x, b, rows, kind: int = GEN_DOMINANT, gamma: float = 0.0) -> np.ndarray:
     """r[rows] of r = b - A x, A regenerated (sampled rows of residual_regen)."""
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     out = np.zeros(len(rows))
-    lib().orc_residual_rows(n, seed, _p(_f64(x)), _p(_f64(b)), rows.ctypes.data_as(ctypes.c_void_p), len(rows),
-                            _p(out))
+    lib().orc_residual_rows(n, seed, kind, gamma, _p(_f64(x)), _p(_f64(b)), rows.ctypes.data_as(ctypes.c_void_p),
+                            len(rows), _p(out))
     return out
 
 
-def hpl_eta_regen(n: int, seed: int, x, b) -> float:
-    return float(lib().orc_hpl_eta_regen(n, seed, _p(_f64(x)), _p(_f64(b))))
+def hpl_eta_regen(n: int, seed: int, x, b, kind: int = GEN_DOMINANT, gamma: float = 0.0,
+                  a_inf: float | None = None) -> float:
+    """HPL scaled residual with A regenerated; a_inf (from anorm_inf_regen) may be passed to skip its pass."""
+    return float(lib().orc_hpl_eta_regen(n, seed, kind, gamma, _p(_f64(x)), _p(_f64(b)),
+                                         -1.0 if a_inf is None else float(a_inf)))
 
 
-def jacobi_regen(n: int, seed: int, b, max_sweeps: int = 200, tol: float = 2.0 ** -50):
+def jacobi_regen(n: int, seed: int, b, max_sweeps: int = 200, tol: float = 2.0 ** -50, kind: int = GEN_DOMINANT,
+                 gamma: float = 0.0):
     x = np.zeros(n)
-    sweeps = lib().orc_jacobi_regen(n, seed, _p(_f64(b)), _p(x), max_sweeps, tol)
+    sweeps = lib().orc_jacobi_regen(n, seed, kind, gamma, _p(_f64(b)), _p(x), max_sweeps, tol)
     return x, int(sweeps)
 
 
@@ -211,9 +240,9 @@ def gmres_ir(A, P, b, restart: int = 30, max_iters: int = 50, tol: float = 16.0,
 
 
 def solve(n: int, seed: int, nrhs: int = 1, restart: int = 30, max_iters: int = 50, tol: float = 16.0,
-          tau: float = 2.0 ** -50):
+          tau: float = 2.0 ** -50, kind: int = GEN_DOMINANT, gamma: float = 0.0):
     """Full oracle solve at small n: generate, FP64 LU, GMRES-IR per RHS."""
-    A, d = generate(n, seed)
+    A, d = generate(n, seed, kind, gamma)
     B = generate_rhs(n, nrhs, seed)
     LU, info = lu_nopiv(A)
     if info:

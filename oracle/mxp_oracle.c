@@ -95,7 +95,22 @@ static double draw_value(uint32_t k)
     return ldexp((double)k, -32) - 0.5;
 }
 
-/* off-diagonal entry A[i,j] (also the value the diagonal's own draw has) */
+/*
+ * Matrix kinds ("Matrix Generation"; "Experimental Results"):
+ *   0 dominant: off-diagonal u(i,j) = draw value in [-1/2, 1/2); diagonal =
+ *     the sum over the whole row (own draw included) of |u(i,j)|;
+ *   1 sqrt(n):  off-diagonal u(i,j); diagonal = u(i,i) + gamma * sqrt(n)
+ *     (each operation rounded once in FP64);
+ *   2 uniform:  every entry 2 u(i,j), in [-1, 1), no diagonal change.
+ */
+typedef struct {
+    int64_t n;
+    uint64_t seed;
+    int kind;
+    double gamma;
+} orc_gen;
+
+/* the draw value u(i,j) of the matrix stream */
 double orc_entry_draw(uint64_t seed, int64_t i, int64_t j)
 {
     return draw_value(orc_draw(seed, 0u, i, j));
@@ -107,33 +122,59 @@ double orc_rhs(uint64_t seed, int64_t i, int64_t r)
     return draw_value(orc_draw(seed, 1u, i, r));
 }
 
-/* diagonal entry: the sum over the whole row (own draw included) of |draw| */
-double orc_diag(int64_t n, uint64_t seed, int64_t i)
+/* off-diagonal entry A[i,j] (i != j) of a kind */
+static double gen_offdiag(const orc_gen *g, int64_t i, int64_t j)
 {
+    double u = orc_entry_draw(g->seed, i, j);
+    return g->kind == 2 ? 2.0 * u : u;
+}
+
+/* diagonal entry A[i,i] of a kind */
+static double gen_diag(const orc_gen *g, int64_t i)
+{
+    if (g->kind == 1) {
+        double shift = g->gamma * sqrt((double)g->n);
+        return orc_entry_draw(g->seed, i, i) + shift;
+    }
+    if (g->kind == 2)
+        return 2.0 * orc_entry_draw(g->seed, i, i);
     double s = 0.0;
-    for (int64_t j = 0; j < n; ++j)
-        s += fabs(orc_entry_draw(seed, i, j));
+    for (int64_t j = 0; j < g->n; ++j)
+        s += fabs(orc_entry_draw(g->seed, i, j));
     return s;
 }
 
-/* A[i,j] of the generated matrix, FP64 */
-double orc_entry(int64_t n, uint64_t seed, int64_t i, int64_t j)
+double orc_diag(int64_t n, uint64_t seed, int kind, double gamma, int64_t i)
 {
-    return (i == j) ? orc_diag(n, seed, i) : orc_entry_draw(seed, i, j);
+    orc_gen g = {n, seed, kind, gamma};
+    return gen_diag(&g, i);
 }
 
-/* dense generation: A column-major (lda >= n), diag[n] (may be NULL) */
-void orc_generate(int64_t n, uint64_t seed, double *A, int64_t lda, double *diag)
+/* A[i,j] of the generated matrix, FP64 */
+double orc_entry(int64_t n, uint64_t seed, int kind, double gamma, int64_t i, int64_t j)
 {
+    orc_gen g = {n, seed, kind, gamma};
+    return (i == j) ? gen_diag(&g, i) : gen_offdiag(&g, i, j);
+}
+
+/* dense generation: A column-major (lda >= n), diag[n] and row_l1[n] (may be NULL) */
+void orc_generate(int64_t n, uint64_t seed, int kind, double gamma, double *A, int64_t lda, double *diag,
+                  double *row_l1)
+{
+    orc_gen g = {n, seed, kind, gamma};
     for (int64_t j = 0; j < n; ++j)
         for (int64_t i = 0; i < n; ++i)
-            A[i + j * lda] = orc_entry_draw(seed, i, j);
+            A[i + j * lda] = (i == j) ? 0.0 : gen_offdiag(&g, i, j);
     for (int64_t i = 0; i < n; ++i) {
-        double s = 0.0;
-        for (int64_t j = 0; j < n; ++j)
-            s += fabs(A[i + j * lda]);
-        A[i + i * lda] = s;
-        if (diag) diag[i] = s;
+        double d = gen_diag(&g, i);
+        A[i + i * lda] = d;
+        if (diag) diag[i] = d;
+        if (row_l1) {
+            double off = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                if (j != i) off += fabs(A[i + j * lda]);
+            row_l1[i] = off + fabs(d);
+        }
     }
 }
 
@@ -145,17 +186,16 @@ void orc_generate_rhs(int64_t n, int64_t nrhs, uint64_t seed, double *B, int64_t
 }
 
 /* ||A||_inf of the generated matrix, regenerating rows (O(n) memory) */
-double orc_anorm_inf_regen(int64_t n, uint64_t seed)
+double orc_anorm_inf_regen(int64_t n, uint64_t seed, int kind, double gamma)
 {
+    orc_gen g = {n, seed, kind, gamma};
     double best = 0.0;
 #pragma omp parallel for reduction(max : best) schedule(static)
     for (int64_t i = 0; i < n; ++i) {
-        double off = 0.0, own = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            double a = fabs(orc_entry_draw(seed, i, j));
-            if (j == i) own = a; else off += a;
-        }
-        double row = off + (off + own); /* off-diagonal sum + diagonal */
+        double off = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i) off += fabs(gen_offdiag(&g, i, j));
+        double row = off + fabs(gen_diag(&g, i));
         if (row > best) best = row;
     }
     return best;
@@ -230,6 +270,56 @@ int64_t orc_lu_nopiv(int64_t n, double *A, int64_t lda)
     return 0;
 }
 
+/*
+ * LU with partial pivoting, in place ("Experimental Results": the standard
+ * FP64 factorisation whose largest pivot Figure 2 reports): for each column
+ * k the entry of largest magnitude on or below the diagonal (the first one
+ * among equals) becomes the pivot, rows k and p are swapped across the whole
+ * matrix, then the column is scaled and the trailing matrix updated.
+ * ipiv[k] = p (0-based row swapped with k).  Returns 0, or the 1-based index
+ * of the first zero pivot (the elimination goes on past it without scaling).
+ */
+int64_t orc_lu_pp(int64_t n, double *A, int64_t lda, int64_t *ipiv)
+{
+    int64_t info = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t p = k;
+        double best = fabs(A[k + k * lda]);
+        for (int64_t i = k + 1; i < n; ++i)
+            if (fabs(A[i + k * lda]) > best) { best = fabs(A[i + k * lda]); p = i; }
+        ipiv[k] = p;
+        if (p != k)
+            for (int64_t j = 0; j < n; ++j) {
+                double t = A[k + j * lda];
+                A[k + j * lda] = A[p + j * lda];
+                A[p + j * lda] = t;
+            }
+        double piv = A[k + k * lda];
+        if (piv == 0.0) {
+            if (!info) info = k + 1;
+            continue;
+        }
+        for (int64_t i = k + 1; i < n; ++i) A[i + k * lda] /= piv;
+        for (int64_t j = k + 1; j < n; ++j) {
+            double ukj = A[k + j * lda];
+            if (ukj == 0.0) continue;
+            for (int64_t i = k + 1; i < n; ++i)
+                A[i + j * lda] -= A[i + k * lda] * ukj;
+        }
+    }
+    return info;
+}
+
+/* x <- P x with the row swaps ipiv of orc_lu_pp, in order */
+void orc_apply_pivots(int64_t n, const int64_t *ipiv, double *x)
+{
+    for (int64_t k = 0; k < n; ++k) {
+        double t = x[k];
+        x[k] = x[ipiv[k]];
+        x[ipiv[k]] = t;
+    }
+}
+
 /* x <- L^-1 x (L unit lower in LU), then x <- U^-1 x */
 void orc_lu_solve(int64_t n, const double *LU, int64_t lda, double *x)
 {
@@ -257,73 +347,85 @@ double orc_hpl_eta(int64_t n, const double *A, int64_t lda, const double *x, con
     return eta;
 }
 
-/* r = b - A x with A regenerated entry by entry (rows in parallel) */
-void orc_residual_regen(int64_t n, uint64_t seed, const double *x, const double *b, double *r)
+/* r_i = b_i - (A x)_i for one row, A regenerated entry by entry (for the
+ * dominant kind the diagonal's sum of |u| is taken in the same pass) */
+static double residual_row(const orc_gen *g, int64_t i, const double *x, const double *b)
 {
-#pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; ++i) {
-        double ax = 0.0, dsum = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            double a = orc_entry_draw(seed, i, j);
+    double ax = 0.0, d;
+    if (g->kind == 0) {
+        double dsum = 0.0;
+        for (int64_t j = 0; j < g->n; ++j) {
+            double a = orc_entry_draw(g->seed, i, j);
             dsum += fabs(a);
             if (j != i) ax += a * x[j];
         }
-        r[i] = b[i] - (ax + dsum * x[i]);
+        d = dsum;
+    } else {
+        for (int64_t j = 0; j < g->n; ++j)
+            if (j != i) ax += gen_offdiag(g, i, j) * x[j];
+        d = gen_diag(g, i);
     }
+    return b[i] - (ax + d * x[i]);
+}
+
+/* r = b - A x with A regenerated entry by entry (rows in parallel) */
+void orc_residual_regen(int64_t n, uint64_t seed, int kind, double gamma, const double *x, const double *b,
+                        double *r)
+{
+    orc_gen g = {n, seed, kind, gamma};
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        r[i] = residual_row(&g, i, x, b);
 }
 
 /* the same residual for the m sampled rows rows[0..m-1] only: out[k] = r[rows[k]] */
-void orc_residual_rows(int64_t n, uint64_t seed, const double *x, const double *b, const int64_t *rows, int64_t m,
-                       double *out)
+void orc_residual_rows(int64_t n, uint64_t seed, int kind, double gamma, const double *x, const double *b,
+                       const int64_t *rows, int64_t m, double *out)
 {
+    orc_gen g = {n, seed, kind, gamma};
 #pragma omp parallel for schedule(static)
-    for (int64_t k = 0; k < m; ++k) {
-        const int64_t i = rows[k];
-        double ax = 0.0, dsum = 0.0;
-        for (int64_t j = 0; j < n; ++j) {
-            double a = orc_entry_draw(seed, i, j);
-            dsum += fabs(a);
-            if (j != i) ax += a * x[j];
-        }
-        out[k] = b[i] - (ax + dsum * x[i]);
-    }
+    for (int64_t k = 0; k < m; ++k)
+        out[k] = residual_row(&g, rows[k], x, b);
 }
 
-/* HPL scaled residual with A regenerated (O(n) memory) */
-double orc_hpl_eta_regen(int64_t n, uint64_t seed, const double *x, const double *b)
+/* HPL scaled residual with A regenerated (O(n) memory); a_inf < 0: computed here */
+double orc_hpl_eta_regen(int64_t n, uint64_t seed, int kind, double gamma, const double *x, const double *b,
+                         double a_inf)
 {
     double *r = (double *)malloc((size_t)n * sizeof(double));
-    orc_residual_regen(n, seed, x, b, r);
+    orc_residual_regen(n, seed, kind, gamma, x, b, r);
+    if (a_inf < 0) a_inf = orc_anorm_inf_regen(n, seed, kind, gamma);
     double eps = ldexp(1.0, -53);
-    double eta = norm_inf_vec(n, r) /
-                 ((orc_anorm_inf_regen(n, seed) * norm_inf_vec(n, x) + norm_inf_vec(n, b)) * (double)n * eps);
+    double eta = norm_inf_vec(n, r) / ((a_inf * norm_inf_vec(n, x) + norm_inf_vec(n, b)) * (double)n * eps);
     free(r);
     return eta;
 }
 
 /*
  * Jacobi iteration x <- D^-1 (b - (A - D) x), A regenerated row by row.
- * Converges for strictly row diagonally dominant A.  Stops when the update
- * is at most tol * ||x||_inf or after max_sweeps.  Returns the sweeps done.
+ * Converges for strictly row diagonally dominant A (the dominant kind).
+ * Stops when the update is at most tol * ||x||_inf or after max_sweeps.
+ * Returns the sweeps done.
  */
-int64_t orc_jacobi_regen(int64_t n, uint64_t seed, const double *b, double *x, int64_t max_sweeps, double tol)
+int64_t orc_jacobi_regen(int64_t n, uint64_t seed, int kind, double gamma, const double *b, double *x,
+                         int64_t max_sweeps, double tol)
 {
+    orc_gen g = {n, seed, kind, gamma};
     double *d = (double *)malloc((size_t)n * sizeof(double));
     double *xn = (double *)malloc((size_t)n * sizeof(double));
     int64_t sweeps = 0;
     for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i)
+        d[i] = gen_diag(&g, i);
     for (; sweeps < max_sweeps;) {
         double dmax = 0.0;
 #pragma omp parallel for schedule(static) reduction(max : dmax)
         for (int64_t i = 0; i < n; ++i) {
-            double off = 0.0, dsum = 0.0;
-            for (int64_t j = 0; j < n; ++j) {
-                double a = orc_entry_draw(seed, i, j);
-                dsum += fabs(a);
-                if (j != i) off += a * x[j];
-            }
-            d[i] = dsum;
-            xn[i] = (b[i] - off) / dsum;
+            double off = 0.0;
+            for (int64_t j = 0; j < n; ++j)
+                if (j != i) off += gen_offdiag(&g, i, j) * x[j];
+            xn[i] = (b[i] - off) / d[i];
             double u = fabs(xn[i] - x[i]);
             if (u > dmax) dmax = u;
         }

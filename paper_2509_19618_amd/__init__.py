@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(HERE, "libmxp.so")
 F64, F32, F16, BF16, F8E4M3 = 0, 1, 2, 3, 4
 OK, EINVAL, EWORKSPACE, EHIP, ESINGULAR, ENOCONV, ECRITERION, PENDING = 0, -1, -2, -3, 1, 2, 3, 4
 SCALE_NONE, SCALE_ROW_EQUIL = 0, 1
+GEN_DOMINANT, GEN_SQRTN, GEN_UNIFORM = 0, 1, 2
 
 _DTYPE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f8": F8E4M3, "e4m3": F8E4M3, "fp8": F8E4M3}
 _TORCH = {F32: torch.float32, F16: torch.float16, BF16: torch.bfloat16, F64: torch.float64}
@@ -39,6 +40,21 @@ class MxpError(RuntimeError):
 class _RhsReport(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int64), ("cycles", ctypes.c_int64), ("eta", ctypes.c_double),
                 ("status", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class FactorLayout(ctypes.Structure):
+    """Byte offsets of the parts of mxp_factor's aux and work buffers (mxp_factor_layout)."""
+    _fields_ = [(k, ctypes.c_size_t) for k in ("T", "Trm", "linv", "uinv", "lsc", "rowscale", "linv_full",
+                                               "uinv_full", "aux_bytes", "Lq", "Uq", "inv_sa", "inv_sb", "info",
+                                               "work_bytes")] + [("op_rows", ctypes.c_int64), ("strips", ctypes.c_int64)]
+
+
+class _FactorItem(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nb", ctypes.c_int64), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("aux", ctypes.c_void_p), ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
+
+
+TILE_256x128, TILE_128x128 = 0, 1
 
 
 class _ServerCfg(ctypes.Structure):
@@ -57,7 +73,8 @@ class _RequestResult(ctypes.Structure):
 class _ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("failed", ctypes.c_int64),
                 ("in_flight", ctypes.c_int64), ("peak_in_flight", ctypes.c_int64), ("arena_bytes", ctypes.c_size_t),
-                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t)]
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes_in_use", ctypes.c_size_t), ("groups", ctypes.c_int64),
+                ("grouped_requests", ctypes.c_int64), ("peak_group", ctypes.c_int64), ("streams", ctypes.c_int64)]
 
 
 _lib = None
@@ -67,20 +84,26 @@ _P, _I64, _U64, _I, _D, _SZ = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, 
 SIGNATURES = [
     ("mxp_last_error", ctypes.c_char_p, []),
     ("mxp_version", ctypes.c_char_p, []),
-    ("mxp_generate", _I, [_I64, _I64, _U64, _I, _P, _I64, _P, _I64, _P, _P, _P]),
+    ("mxp_generate", _I, [_I64, _I64, _U64, _I, _D, _I, _P, _I64, _P, _I64, _P, _P, _P, _P]),
     ("mxp_factor_aux_bytes", _SZ, [_I64, _I64]),
     ("mxp_factor_work_bytes", _SZ, [_I64, _I64, _I]),
     ("mxp_factor", _I, [_I64, _I64, _I, _I, _I, _P, _P, _I64, _P, _P, _SZ, _P, _P]),
+    ("mxp_factor_get_layout", _I, [_I64, _I64, _I, _P]),
+    ("mxp_factor_group", _I, [_I, _P, _I, _I, _I, _P, _P]),
     ("mxp_solve_work_bytes", _SZ, [_I64, _I64, _I]),
-    ("mxp_solve_ir", _I, [_I64, _I64, _I, _I, _U64, _P, _I64, _P, _P, _P, _P, _I64, _P, _I64, _I64, _I, _I, _D, _D,
-                          _P, _P, _SZ, _P]),
+    ("mxp_solve_ir", _I, [_I64, _I64, _I, _I, _U64, _I, _P, _I64, _P, _P, _P, _P, _I64, _P, _I64, _I64, _I, _I, _D,
+                          _D, _P, _P, _SZ, _P]),
     ("mxp_residual_work_bytes", _SZ, [_I64, _I64]),
-    ("mxp_residual", _I, [_I64, _U64, _P, _P, _I64, _P, _I64, _P, _I64, _I64, _P, _SZ, _P]),
+    ("mxp_residual", _I, [_I64, _U64, _I, _P, _P, _I64, _P, _I64, _P, _I64, _I64, _P, _SZ, _P]),
     ("mxp_apply_prec_work_bytes", _SZ, [_I64, _I64]),
     ("mxp_apply_prec", _I, [_I64, _I64, _I, _I, _P, _I64, _P, _P, _I64, _P, _I64, _I64, _P, _SZ, _P]),
     ("mxp_hpl_eta_work_bytes", _SZ, [_I64]),
-    ("mxp_hpl_eta", _I, [_I64, _U64, _P, _P, _P, _P, _P, _P, _SZ, _P]),
+    ("mxp_hpl_eta", _I, [_I64, _U64, _I, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     ("mxp_trailing_update", _I, [_I64, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P]),
+    ("mxp_lu64_work_bytes", _SZ, [_I64]),
+    ("mxp_trailing_update64", _I, [_I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P]),
+    ("mxp_lu64_factor", _I, [_I64, _P, _I64, _P, _I, _P, _SZ, _P, _P]),
+    ("mxp_lu64_solve", _I, [_I64, _P, _I64, _P, _P, _I64, _I64, _P]),
     ("mxp_profile_enable", _I, [_I]),
     ("mxp_profile_reset", _I, []),
     ("mxp_profile_read", _I, [_I, _P, _P, _P, _P]),
@@ -92,10 +115,11 @@ SIGNATURES = [
     ("mxp_server_drain", _I, [_P]),
     ("mxp_server_get_stats", _I, [_P, _P]),
     ("mxp_server_block_size", _I64, [_P, _I64]),
+    ("mxp_server_tile", _I, [_P, _I64]),
     ("mxp_server_destroy", _I, [_P]),
 ]
 
-PROF_GEMM, PROF_TRSM, PROF_DIAG, PROF_PREC, PROF_REGEN = 0, 1, 2, 3, 4
+PROF_GEMM, PROF_TRSM, PROF_DIAG, PROF_PREC, PROF_REGEN, PROF_GEMM64 = 0, 1, 2, 3, 4, 6
 
 
 def lib():
@@ -160,19 +184,23 @@ class Problem:
     B: torch.Tensor | None      # (nrhs, n) FP64, column-major n x nrhs
     diag: torch.Tensor          # (n,) FP64
     a_inf: torch.Tensor         # (1,) FP64
+    kind: int = GEN_DOMINANT
+    gamma: float = 0.0
+    row_l1: torch.Tensor | None = None   # (n,) FP64
 
 
 def mxp_generate(n: int, nrhs: int, seed: int, store="f16", with_matrix: bool = True, lda: int | None = None,
-                 device="cuda", stream=None) -> Problem:
+                 device="cuda", stream=None, kind: int = GEN_DOMINANT, gamma: float = 0.0) -> Problem:
     st = dtype_code(store)
     lda = lda or round_up(n, 128)
     A = torch.empty((n, lda), dtype=_TORCH[st], device=device) if with_matrix else None
     B = torch.empty((max(nrhs, 1), n), dtype=torch.float64, device=device)
     diag = torch.empty(n, dtype=torch.float64, device=device)
+    row_l1 = torch.empty(n, dtype=torch.float64, device=device)
     a_inf = torch.empty(1, dtype=torch.float64, device=device)
-    _check(lib().mxp_generate(n, nrhs, seed, st, _ptr(A), lda, _ptr(B) if nrhs else None, n, _ptr(diag),
-                              _ptr(a_inf), _stream(stream)))
-    return Problem(n, nrhs, seed, st, A, lda, B if nrhs else None, diag, a_inf)
+    _check(lib().mxp_generate(n, nrhs, seed, kind, gamma, st, _ptr(A), lda, _ptr(B) if nrhs else None, n, _ptr(diag),
+                              _ptr(row_l1), _ptr(a_inf), _stream(stream)))
+    return Problem(n, nrhs, seed, st, A, lda, B if nrhs else None, diag, a_inf, kind, gamma, row_l1)
 
 
 # ------------------------------------------------------------------ factor
@@ -187,6 +215,7 @@ class Factor:
     aux: torch.Tensor
     info: int
     status: int
+    work: torch.Tensor | None = None
 
 
 def mxp_factor(prob: Problem, nb: int, update="f16", scaling: int = SCALE_NONE, work: torch.Tensor | None = None,
@@ -204,7 +233,34 @@ def mxp_factor(prob: Problem, nb: int, update="f16", scaling: int = SCALE_NONE, 
     st = L.mxp_factor(n, nb, up, prob.store, scaling, _ptr(prob.diag), _ptr(prob.A), prob.lda, _ptr(aux),
                       _ptr(work), work.numel(), ctypes.byref(info) if sync_info else None, _stream(stream))
     _check(st, allow_positive=True)
-    return Factor(n, nb, up, prob.store, prob.A, prob.lda, aux, int(info.value), st)
+    return Factor(n, nb, up, prob.store, prob.A, prob.lda, aux, int(info.value), st, work)
+
+
+def mxp_factor_group(probs, nbs, update="bf16", tile: int = TILE_256x128, stream=None):
+    """Factor several problems (same storage format) with one launch per kernel
+    and block step (mxp_factor_group); returns a Factor per problem."""
+    up = dtype_code(update)
+    L = lib()
+    items = (_FactorItem * len(probs))()
+    facs = []
+    for i, (prob, nb) in enumerate(zip(probs, nbs)):
+        aux = _bytes(L.mxp_factor_aux_bytes(prob.n, nb), prob.A.device)
+        work = _bytes(L.mxp_factor_work_bytes(prob.n, nb, up), prob.A.device)
+        items[i] = _FactorItem(prob.n, nb, prob.A.data_ptr(), prob.lda, aux.data_ptr(), work.data_ptr(), work.numel())
+        facs.append(Factor(prob.n, nb, up, prob.store, prob.A, prob.lda, aux, 0, 0, work))
+    info = (ctypes.c_int64 * len(probs))()
+    st = L.mxp_factor_group(len(probs), items, up, probs[0].store, tile, info, _stream(stream))
+    _check(st, allow_positive=True)
+    for f, v in zip(facs, info):
+        f.info, f.status = int(v), st
+    return facs
+
+
+def factor_layout(n: int, nb: int, update="f16") -> FactorLayout:
+    """Offsets of the parts of mxp_factor's aux and work buffers."""
+    out = FactorLayout()
+    _check(lib().mxp_factor_get_layout(n, nb, dtype_code(update), ctypes.byref(out)))
+    return out
 
 
 # ------------------------------------------------------------------ solve
@@ -229,7 +285,7 @@ def mxp_solve_ir(prob: Problem, fac: Factor, B: torch.Tensor | None = None, rest
     if X is None:
         X = torch.empty((nrhs, n), dtype=torch.float64, device=B.device)
     reps = (_RhsReport * nrhs)()
-    code = L.mxp_solve_ir(n, fac.nb, fac.update, fac.store, prob.seed, _ptr(fac.LU), fac.lda, _ptr(fac.aux),
+    code = L.mxp_solve_ir(n, fac.nb, fac.update, fac.store, prob.seed, prob.kind, _ptr(fac.LU), fac.lda, _ptr(fac.aux),
                           _ptr(prob.diag), _ptr(prob.a_inf), _ptr(B), n, _ptr(X), n, nrhs, restart, max_iters, tol,
                           tau, reps, _ptr(work), work.numel(), _stream(stream))
     _check(code, allow_positive=True)
@@ -243,8 +299,8 @@ def mxp_residual(prob: Problem, X: torch.Tensor, B: torch.Tensor | None = None, 
     L = lib()
     work = _bytes(L.mxp_residual_work_bytes(n, nrhs), X.device)
     R = torch.empty((nrhs, n), dtype=torch.float64, device=X.device)
-    _check(L.mxp_residual(n, prob.seed, _ptr(prob.diag), _ptr(X), n, _ptr(B), n, _ptr(R), n, nrhs, _ptr(work),
-                          work.numel(), _stream(stream)))
+    _check(L.mxp_residual(n, prob.seed, prob.kind, _ptr(prob.diag), _ptr(X), n, _ptr(B), n, _ptr(R), n, nrhs,
+                          _ptr(work), work.numel(), _stream(stream)))
     return R
 
 
@@ -264,8 +320,8 @@ def mxp_hpl_eta(prob: Problem, x: torch.Tensor, b: torch.Tensor, stream=None) ->
     L = lib()
     work = _bytes(L.mxp_hpl_eta_work_bytes(n), x.device)
     eta = ctypes.c_double(0.0)
-    _check(L.mxp_hpl_eta(n, prob.seed, _ptr(prob.diag), _ptr(prob.a_inf), _ptr(x), _ptr(b), ctypes.byref(eta),
-                         _ptr(work), work.numel(), _stream(stream)))
+    _check(L.mxp_hpl_eta(n, prob.seed, prob.kind, _ptr(prob.diag), _ptr(prob.a_inf), _ptr(x), _ptr(b),
+                         ctypes.byref(eta), _ptr(work), work.numel(), _stream(stream)))
     return float(eta.value)
 
 
@@ -276,6 +332,49 @@ def mxp_trailing_update(C: torch.Tensor, ldc: int, M: int, N: int, K: int, updat
                                      _ptr(Bq), _ptr(inv_sa), _ptr(inv_sb), _stream(stream)))
 
 
+# ------------------------------------------------------------------ FP64 LU
+@dataclass
+class Factor64:
+    n: int
+    LU: torch.Tensor           # (n, lda) FP64 storage, column-major L\U
+    lda: int
+    ipiv: torch.Tensor | None  # (n,) int64, 0-based swap rows; None without pivoting
+    info: int
+    status: int
+
+
+GEMM64_OWN, GEMM64_ROCBLAS = 0, 1
+
+
+def mxp_lu64_factor(A: torch.Tensor, n: int, lda: int, pivot: bool, sync_info: bool = True,
+                    work: torch.Tensor | None = None, stream=None, gemm: int = GEMM64_OWN) -> Factor64:
+    """FP64 LU in place of A ((n, lda) FP64 storage), with or without partial
+    pivoting; gemm: the trailing update (GEMM64_OWN or GEMM64_ROCBLAS)."""
+    L = lib()
+    if work is None:
+        work = _bytes(L.mxp_lu64_work_bytes(n), A.device)
+    ipiv = torch.empty(n, dtype=torch.int64, device=A.device) if pivot else None
+    info = ctypes.c_int64(0)
+    st = L.mxp_lu64_factor(n, _ptr(A), lda, _ptr(ipiv), gemm, _ptr(work), work.numel(),
+                           ctypes.byref(info) if sync_info else None, _stream(stream))
+    _check(st, allow_positive=True)
+    return Factor64(n, A, lda, ipiv, int(info.value), st)
+
+
+def mxp_trailing_update64(C: torch.Tensor, ldc: int, M: int, N: int, K: int, A: torch.Tensor, lda: int,
+                          B: torch.Tensor, ldb: int, stream=None) -> None:
+    """C <- C - A B in FP64 (column-major, see include/mxp.h)."""
+    _check(lib().mxp_trailing_update64(M, N, K, _ptr(C), ldc, _ptr(A), lda, _ptr(B), ldb, _stream(stream)))
+
+
+def mxp_lu64_solve(fac: Factor64, B: torch.Tensor, stream=None) -> torch.Tensor:
+    """X = U^-1 L^-1 P B for B of shape (nrhs, n) FP64 (a new tensor)."""
+    X = B.clone()
+    _check(lib().mxp_lu64_solve(fac.n, _ptr(fac.LU), fac.lda, _ptr(fac.ipiv), _ptr(X), fac.n, X.shape[0],
+                                _stream(stream)))
+    return X
+
+
 def exported_symbols():
     return [name for name, _, _ in SIGNATURES]
 
@@ -284,7 +383,7 @@ def profile_enable(on: bool = True, classes=None) -> None:
     """Time the given kernel classes (PROF_*; all when None) with HIP events, or stop timing."""
     mask = 0
     if on:
-        mask = (1 << 6) - 1 if classes is None else sum(1 << int(c) for c in set(classes))
+        mask = (1 << 7) - 1 if classes is None else sum(1 << int(c) for c in set(classes))
     _check(lib().mxp_profile_enable(mask))
 
 
@@ -381,6 +480,10 @@ class Server:
 
     def block_size(self, n: int) -> int:
         return int(lib().mxp_server_block_size(self._h, n))
+
+    def tile(self, n: int) -> int:
+        """trailing-update tile (TILE_256x128 / TILE_128x128) of a request of size n"""
+        return int(lib().mxp_server_tile(self._h, n))
 
     def close(self) -> None:
         if getattr(self, "_h", None):

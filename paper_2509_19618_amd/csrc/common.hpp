@@ -232,6 +232,40 @@ MXP_DEV float pow2_scale(float amax, int target) {
     return ldexpf(1.0f, p);
 }
 
+// ------------------------------------------------------------------ cross-work-group hand-over
+// Kernels that hand data from one work-group to another (the diagonal-block
+// LU, the dataflow substitution) write and read every shared value with
+// agent-scope atomic accesses: on gfx950 these go to the device's coherence
+// point (sc1), past any cache that could hold a stale or unwritten copy.
+// The producer then waits until all of its stores are acknowledged
+// (s_waitcnt vmcnt(0)) before it raises the flag or counter; the consumer
+// issues its data loads only after its load of the flag has returned.  That
+// is the whole of an agent-scope release / acquire for data that never sits
+// in a non-coherent cache: the compiler's release fence adds a write-back of
+// the XCD's L2 (buffer_wbl2) and its acquire fence an L2 invalidation
+// (buffer_inv), which matter only for ordinary cached stores and loads.
+// With MXP_SYNC = 2 the kernels use those fences (release and acquire in
+// the language's memory model); measured on the MI355X they cost 9 % of the
+// n = 32768 solve (327 vs 359 TFLOP/s: the write-backs also disturb the
+// concurrent trailing update), so the default is the hardware form above.
+#ifndef MXP_SYNC
+#define MXP_SYNC 0
+#endif
+// before a flag or counter publishes this thread's stores to other work-groups
+MXP_DEV void sync_release() {
+#if MXP_SYNC >= 1
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+#else
+    __builtin_amdgcn_s_waitcnt(0);
+#endif
+}
+// after a flag or counter seen set, before the published data is read
+MXP_DEV void sync_acquire() {
+#if MXP_SYNC >= 2
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+#endif
+}
+
 // ------------------------------------------------------------------ reductions
 MXP_DEV double warp_sum(double v) {
 #pragma unroll

@@ -30,10 +30,13 @@
 // Work-groups that start late simply join the current phase, so the leader
 // never waits for a helper to be scheduled.  T and the tile inverses are
 // read and written with device-scope accesses (they go to the device's
-// coherence point), a wave's stores to T are acknowledged before it counts a
-// task done (the final copies to A and Trm, read only after the launch, are
-// written after that), and every wait is bounded: on expiry it records an error in *info
-// and the wave exits.
+// coherence point).  A wave counts a task done after a release of its stores
+// to T (sync_release: the wave's stores acknowledged), the wave that closes
+// a phase opens the next one the same way, and a wave that sees a phase open
+// reads after it (sync_acquire; see common.hpp for why the hardware form of
+// these needs no cache maintenance).  The final copies to A and Trm, read
+// only after the launch, are written after the completion.  Every wait is
+// bounded: on expiry it records an error in *info and the wave exits.
 //
 // Every 32 x 32 x 32 product is one wave's chain of sixteen
 // v_mfma_f32_32x32x2f32; a substitution is one wave's chain of FMAs with
@@ -144,12 +147,37 @@ MXP_DEV int phase_target(int ph, int P) { return phase_claims(ph, P) + (is_lphas
 
 }  // namespace
 
+struct DiagOne {
+    void* A;
+    int64_t lda, k;
+    int kb, kbp, ldt, wgs;
+    float *T, *Trm, *linv, *uinv;
+    int* sync;
+    unsigned long long* info;
+};
+struct DiagGroup {
+    DiagOne g[GEMM_GROUP_MAX];
+    int count;
+};
+
+// One launch factors the diagonal blocks of a group of factorisations (one
+// per request of the solve server, or a single one): blockIdx.y picks the
+// block, each with its own phase counters; work-groups beyond a block's
+// count leave at once.
 template <int ST>
-__global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int64_t lda, int64_t k, int kb, int kbp,
-                                                float* __restrict__ T, float* __restrict__ Trm, int ldt,
-                                                float* __restrict__ linv, float* __restrict__ uinv, int* sync,
-                                                unsigned long long* info) {
+__global__ __launch_bounds__(DT, 2) void k_diag_lu(const DiagGroup grp) {
     extern __shared__ __attribute__((aligned(16))) float dsm[];
+    const DiagOne& G = grp.g[blockIdx.y];
+    if ((int)blockIdx.x >= G.wgs) return;
+    typename Store<ST>::T* A = (typename Store<ST>::T*)G.A;
+    const int64_t lda = G.lda, k = G.k;
+    const int kb = G.kb, kbp = G.kbp, ldt = G.ldt;
+    float* __restrict__ T = G.T;
+    float* __restrict__ Trm = G.Trm;
+    float* __restrict__ linv = G.linv;
+    float* __restrict__ uinv = G.uinv;
+    int* sync = G.sync;
+    unsigned long long* info = G.info;
     const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     // lane-derived values, remade through opaque() before every task (see
     // refresh below)
@@ -201,7 +229,8 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
     auto fail = [&]() {
         if (lane == 0) atomicMin(info, 1ull << 62);
     };
-    // bounded wait until the open phase is at least ph
+    // bounded wait until the open phase is at least ph (polled with relaxed
+    // loads), then an acquire: the stores of the phases before ph are visible
     auto wait_phase = [&](int ph) -> bool {
         unsigned it = 0;
         while (ild(phase) < ph) {
@@ -211,19 +240,24 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(typename Store<ST>::T* A, int
             }
             __builtin_amdgcn_s_sleep(1);
         }
+        sync_acquire();
         return true;
     };
-    // this wave's stores are acknowledged, then one more completion of ph; the
-    // completion that closes the phase opens the next non-empty one
+    // one more completion of ph, released by every lane (each lane counts
+    // itself: one atomic of +64 per wave after the compiler combines the
+    // lanes, so a phase closes at 64 completions per task); the wave that
+    // closes the phase acquires the others' completions and opens the next
+    // non-empty phase with a release
     auto complete = [&](int ph) {
-        __builtin_amdgcn_s_waitcnt(0);
-        int old = 0;
-        if (lane == 0) old = atomicAdd(&dones[ph], 1);
+        sync_release();
+        int old = __hip_atomic_fetch_add(&dones[ph], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         old = __builtin_amdgcn_readfirstlane(old);
-        if (old + 1 == phase_target(ph, P)) {
+        if (old + 64 == 64 * phase_target(ph, P)) {
             // T(P-1) is the only empty phase
             const int nx = (ph + 1 == 2 * P - 1) ? ph + 2 : ph + 1;
-            if (lane == 0) __hip_atomic_store(phase, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            sync_acquire();
+            sync_release();
+            __hip_atomic_store(phase, nx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     };
     auto claim = [&](int ph) -> int {
@@ -613,30 +647,46 @@ size_t diag_lu_smem() { return (size_t)(2 * DW) * TILE_F * sizeof(float); }
 size_t diag_sync_words() { return 1 + 2 * NPMAX; }
 
 template <int ST>
-static hipError_t diag_lu_typed(void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
-                                float* linv, float* uinv, int* sync, unsigned long long* info, hipStream_t s) {
+static hipError_t diag_lu_typed(const DiagCall* calls, int count, hipStream_t s) {
     static const hipError_t attr = hipFuncSetAttribute((const void*)k_diag_lu<ST>,
                                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)diag_lu_smem());
     if (attr) return attr;
-    // helpers scale with the work (a 512 block: one leader work-group and
-    // fifteen helpers; the early update phases have up to 225 tile tasks)
-    const int P = kbp / 32;
-    int wgs = P;
-    wgs = wgs < 1 ? 1 : (wgs > 16 ? 16 : wgs);
-    k_diag_lu<ST><<<wgs, DT, diag_lu_smem(), s>>>((typename Store<ST>::T*)A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv,
-                                                 sync, info);
+    DiagGroup grp;
+    int wmax = 1;
+    for (int i = 0; i < count; ++i) {
+        const DiagCall& c = calls[i];
+        DiagOne& g = grp.g[i];
+        g.A = c.A; g.lda = c.lda; g.k = c.k; g.kb = c.kb; g.kbp = c.kbp; g.ldt = c.ldt;
+        g.T = c.T; g.Trm = c.Trm; g.linv = c.linv; g.uinv = c.uinv; g.sync = c.sync; g.info = c.info;
+        // helpers scale with the work (a 512 block: one leader work-group and
+        // fifteen helpers; the early update phases have up to 225 tile tasks)
+        const int P = c.kbp / 32;
+        g.wgs = P < 1 ? 1 : (P > 16 ? 16 : P);
+        wmax = g.wgs > wmax ? g.wgs : wmax;
+    }
+    grp.count = count;
+    k_diag_lu<ST><<<dim3(wmax, count), DT, diag_lu_smem(), s>>>(grp);
     return hipGetLastError();
+}
+
+hipError_t diag_lu_group(int store, const DiagCall* calls, int count, hipStream_t s) {
+    if (count < 1 || count > GEMM_GROUP_MAX) return hipErrorInvalidValue;
+    for (int i = 0; i < count; ++i) {
+        const DiagCall& c = calls[i];
+        if (c.kb < 1 || c.kbp % 64 || c.kbp > c.ldt || c.kb > c.kbp || c.kbp > 1024) return hipErrorInvalidValue;
+    }
+    switch (store) {
+    case F32: return diag_lu_typed<F32>(calls, count, s);
+    case F16: return diag_lu_typed<F16>(calls, count, s);
+    case BF16: return diag_lu_typed<BF16>(calls, count, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
                    float* linv, float* uinv, int* sync, unsigned long long* info, hipStream_t s) {
-    if (kb < 1 || kbp % 64 || kbp > ldt || kb > kbp || kbp > 1024) return hipErrorInvalidValue;
-    switch (store) {
-    case F32: return diag_lu_typed<F32>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, sync, info, s);
-    case F16: return diag_lu_typed<F16>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, sync, info, s);
-    case BF16: return diag_lu_typed<BF16>(A, lda, k, kb, kbp, T, Trm, ldt, linv, uinv, sync, info, s);
-    default: return hipErrorInvalidValue;
-    }
+    DiagCall c{A, lda, k, kb, kbp, ldt, T, Trm, linv, uinv, sync, info};
+    return diag_lu_group(store, &c, 1, s);
 }
 
 }  // namespace mxp

@@ -95,15 +95,16 @@ template <> struct Quad<BF16> {
     }
 };
 
-// Work-group tile TM x TN = 256 x 128, 4 waves in a 2 x 2 grid, each wave
-// 128 x 64 (8 blocks of 32 x 32, accumulators in AGPRs).  Two work-groups
-// share a CU (at most 256 registers per wave, 72 KB of LDS each), so that
-// one work-group's epilogue overlaps the other's MFMA loop.
-constexpr int TM = 256, TN = 128;
+// Work-group tile TMv x TN (TMv = 256 or 128, TN = 128), 4 waves in a 2 x 2
+// grid, each wave (TMv/2) x 64 (blocks of 32 x 32, accumulators in AGPRs).
+// With TMv = 256 two work-groups share a CU (at most 256 registers per wave,
+// 72 KB of LDS each), so that one work-group's epilogue overlaps the other's
+// MFMA loop; TMv = 128 gives twice as many tiles for small trailing matrices.
+constexpr int TN = 128;
 constexpr int GBK = 64;            // K bytes per stage
 constexpr int NBUF = 3;            // stages in LDS: two copies in flight while one is read
 constexpr int GCH = GBK / 16;      // 16-byte chunks per operand row
-constexpr int SA = TM * GBK, SB = TN * GBK;   // bytes of one A / B stage
+constexpr int SB = TN * GBK;       // bytes of one B stage
 constexpr int GGROUP = 8;          // tile rows per group in the tile order
 
 // Direct global->LDS copy of 16 bytes per lane: lane L lands at l + 16 L
@@ -129,6 +130,16 @@ template <int NIS, int NC, int Y> MXP_DEV void wait_case(int y, bool c) {
     }
 }
 
+
+// c - a d with d a power of two (a d exact): one rounding to FP32; the
+// rounding to the storage format stays a separate step in every epilogue
+// (the compiler would otherwise fuse some of them into one FP16 rounding,
+// and the two epilogues would differ in the last bit)
+MXP_DEV float sub_scaled(float c, float a, float d) {
+    float v = __builtin_fmaf(-a, d, c);
+    asm volatile("" : "+v"(v));
+    return v;
+}
 
 // byte offset of (row, byte b) in an operand stage: 16-byte chunks XOR-swizzled by row
 MXP_DEV int swz(int row, int b) { return row * GBK + ((((b >> 4) ^ (row & (GCH - 1))) << 4) | (b & 15)); }
@@ -162,31 +173,47 @@ template <> struct Frag<F8> {
     }
 };
 
+// One launch serves a group of independent updates (one per request of the
+// solve server, or a single one): the tiles of the group's updates are
+// numbered one after another and every work-group finds its update by its
+// tile number.  Passed by value (kernel arguments).
+struct GemmOne {
+    void* C;
+    int64_t ldc, M, N;
+    const char* Aq;
+    const char* Bq;
+    const float* inv_sa;
+    const float* inv_sb;
+    int K, tiles_m, tiles_n, tile_end, vec_ok, pad;
+};
+struct GemmGroup {
+    GemmOne g[GEMM_GROUP_MAX];
+    int count, per_xcd;
+};
+
 // Operands: K-major rows, copied GBK bytes of K per stage straight into
 // XOR-swizzled LDS buffers (no staging registers), NBUF stages deep; each
 // k-step reads its fragments from LDS (the other work-group on the SIMD
 // covers their latency).  Epilogue, full tiles with 16-bit C: the freed LDS
-// holds the C tile (read and written with coalesced 16-byte accesses, 512
+// holds the C tile (read and written with coalesced 16-byte accesses, TMv*2
 // bytes per column), updated in place in the MFMA layout; the first half of
 // the tile is loaded into registers at the first stage, so that its HBM
 // reads overlap the MFMA loop (the whole tile would not fit beside the
 // accumulators), the second half in the epilogue.  Other tiles update C
 // directly with guarded accesses.
-template <int OP, int ST>
-__global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C, int64_t ldc, int64_t M, int64_t N,
-                                                        int K, const char* __restrict__ Aq,
-                                                        const char* __restrict__ Bq,
-                                                        const float* __restrict__ inv_sa,
-                                                        const float* __restrict__ inv_sb, int tiles_m, int tiles_n,
-                                                        int per_xcd, int vec_ok) {
+template <int OP, int ST, int TMv>
+__global__ __launch_bounds__(256, 2) void k_gemm_update(const GemmGroup grp) {
     typedef typename Store<ST>::T CT;
     typedef typename Frag<OP>::T FT;
+    constexpr int SA = TMv * GBK;          // bytes of one A stage
+    constexpr int WR = TMv / 2;            // rows of a wave's tile
+    constexpr int NA = TMv / 64;           // 32-row blocks of a wave's tile
     constexpr int KB = Mfma<OP>::KB;
     constexpr int NKS = GBK / KB;          // k-steps per stage
     constexpr int RPI = 64 / GCH;          // operand rows per 1 KB copy instruction
-    constexpr int NIA = TM / RPI / 4, NIB = TN / RPI / 4;   // copy instructions per wave and stage
+    constexpr int NIA = TMv / RPI / 4, NIB = TN / RPI / 4;   // copy instructions per wave and stage
     constexpr int NIS = NIA + NIB;
-    constexpr int CP = TM * (int)sizeof(CT) + 16;  // LDS pitch of a C column in the epilogue
+    constexpr int CP = TMv * (int)sizeof(CT) + 16;  // LDS pitch of a C column in the epilogue
     extern __shared__ __attribute__((aligned(16))) char lds[];
     char* sA = lds;
     char* sB = lds + NBUF * SA;
@@ -194,18 +221,28 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C
     const int wm = wave & 1, wn = wave >> 1;
     // work-group j of XCD x (x = blockIdx % 8) takes tile x*per_xcd + j of its XCD's contiguous range
     const int xcd = (int)(blockIdx.x % 8);
-    const int lin = xcd * per_xcd + (int)(blockIdx.x / 8);
-    if (lin >= min((xcd + 1) * per_xcd, tiles_m * tiles_n)) return;
+    const int glin = xcd * grp.per_xcd + (int)(blockIdx.x / 8);
+    const int total = grp.g[grp.count - 1].tile_end;
+    if (glin >= min((xcd + 1) * grp.per_xcd, total)) return;
+    int d = 0;
+    while (glin >= grp.g[d].tile_end) ++d;
+    const GemmOne& G = grp.g[d];
+    CT* C = (CT*)G.C;
+    const int64_t ldc = G.ldc, M = G.M, N = G.N;
+    const int K = G.K, tiles_m = G.tiles_m, tiles_n = G.tiles_n, vec_ok = G.vec_ok;
+    const float* __restrict__ inv_sa = G.inv_sa;
+    const float* __restrict__ inv_sb = G.inv_sb;
+    const int lin = glin - (d > 0 ? grp.g[d - 1].tile_end : 0);
     const int group_size = GGROUP * tiles_n;
     const int first_m = (lin / group_size) * GGROUP;
     const int gm = (tiles_m - first_m) < GGROUP ? (tiles_m - first_m) : GGROUP;
     const int tm = first_m + (lin % group_size) % gm;
     const int tn = (lin % group_size) / gm;
-    const int64_t row0 = (int64_t)tm * TM, col0 = (int64_t)tn * TN;
+    const int64_t row0 = (int64_t)tm * TMv, col0 = (int64_t)tn * TN;
     constexpr int eb = sizeof(typename Operand<OP>::T);
     const int64_t Kbytes = (int64_t)K * eb;
-    const char* gA = Aq + row0 * Kbytes;
-    const char* gB = Bq + col0 * Kbytes;
+    const char* gA = G.Aq + row0 * Kbytes;
+    const char* gB = G.Bq + col0 * Kbytes;
     const int nst = (int)(Kbytes / GBK);
     const int lr = lane & 31, lh = lane >> 5;
     const int l_row = lane / GCH, l_pch = lane % GCH;
@@ -226,17 +263,17 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C
             dma16(gB + (int64_t)row * Kbytes + (int64_t)st * GBK + lch * 16, sB + buf * SB + j * 1024);
         }
     };
-    f16v acc[4][2];
+    f16v acc[NA][2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < NA; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    const bool full = vec_ok && (row0 + TM <= M) && (col0 + TN <= N);
+    const bool full = vec_ok && (row0 + TMv <= M) && (col0 + TN <= N);
     constexpr bool c16 = sizeof(CT) == 2;
     const bool cpre = c16 && full;
-    constexpr int COLB = TM * 2;           // bytes of a tile column
+    constexpr int COLB = TMv * 2;          // bytes of a tile column
     constexpr int LPC = COLB / 16;         // lanes per column
     constexpr int CPI = 64 / LPC;          // columns per wave instruction
     constexpr int NIT = TN / 4 / CPI;      // instructions per wave
@@ -265,14 +302,14 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C
         const char* B0 = sB + (st % NBUF) * SB;
 #pragma unroll
         for (int ks = 0; ks < NKS; ++ks) {
-            FT ac[4], bc[2];
+            FT ac[NA], bc[2];
             const int boff = ks * KB + lh * (KB / 2);
 #pragma unroll
-            for (int a = 0; a < 4; ++a) ac[a] = Frag<OP>::ld(A0, wm * 128 + a * 32 + lr, boff);
+            for (int a = 0; a < NA; ++a) ac[a] = Frag<OP>::ld(A0, wm * WR + a * 32 + lr, boff);
 #pragma unroll
             for (int b = 0; b < 2; ++b) bc[b] = Frag<OP>::ld(B0, wn * 64 + b * 32 + lr, boff);
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < NA; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) acc[a][b] = Frag<OP>::mma(ac[a], bc[b], acc[a][b]);
         }
@@ -292,19 +329,19 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C
             }
             __syncthreads();
 #pragma unroll
-            for (int a = 0; a < 4; ++a) {
-                const float ia = inv_sa[(row0 + wm * 128 + a * 32) / 32];
+            for (int a = 0; a < NA; ++a) {
+                const float ia = inv_sa[(row0 + wm * WR + a * 32) / 32];
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
-                    const float d = ia * inv_sb[(col0 + wn * 64 + b * 32) / 32];
+                    const float dd = ia * inv_sb[(col0 + wn * 64 + b * 32) / 32];
                     const int c = wn * 64 + b * 32 + lr;
 #pragma unroll
                     for (int g = 0; g < 4; ++g) {
-                        CT* p = (CT*)(lds + c * CP) + wm * 128 + a * 32 + 8 * g + 4 * lh;
+                        CT* p = (CT*)(lds + c * CP) + wm * WR + a * 32 + 8 * g + 4 * lh;
                         float cv[4], v[4];
                         Quad<ST>::load(p, cv);
 #pragma unroll
-                        for (int q = 0; q < 4; ++q) v[q] = cv[q] - acc[a][b][g * 4 + q] * d;
+                        for (int q = 0; q < 4; ++q) v[q] = sub_scaled(cv[q], acc[a][b][g * 4 + q], dd);
                         Quad<ST>::store(p, v);
                     }
                 }
@@ -321,13 +358,13 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C
     }
     // direct epilogue (FP32 storage, edge tiles): C - acc * d, quads of 4 rows
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t rb = row0 + wm * 128 + a * 32;
+    for (int a = 0; a < NA; ++a) {
+        const int64_t rb = row0 + wm * WR + a * 32;
         const float ia = inv_sa[rb / 32];
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int64_t cb = col0 + wn * 64 + b * 32;
-            const float d = ia * inv_sb[cb / 32];
+            const float dd = ia * inv_sb[cb / 32];
             const int64_t col = cb + lr;
             if (col >= N) continue;
 #pragma unroll
@@ -340,7 +377,7 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C
                 else
                     for (int q = 0; q < 4; ++q) c[q] = (r + q < M) ? Store<ST>::load(p, q) : 0.0f;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) v[q] = c[q] - acc[a][b][g * 4 + q] * d;
+                for (int q = 0; q < 4; ++q) v[q] = sub_scaled(c[q], acc[a][b][g * 4 + q], dd);
                 if (quad) Quad<ST>::store(p, v);
                 else
                     for (int q = 0; q < 4; ++q)
@@ -350,32 +387,51 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(typename Store<ST>::T* C
     }
 }
 
+template <int TMv>
 static constexpr int gemm_lds_bytes() {
-    return NBUF * (SA + SB) > TN * (TM * 2 + 16) ? NBUF * (SA + SB) : TN * (TM * 2 + 16);
+    return NBUF * (TMv * GBK + SB) > TN * (TMv * 2 + 16) ? NBUF * (TMv * GBK + SB) : TN * (TMv * 2 + 16);
 }
 
-template <int OP, int ST>
-static hipError_t gemm_typed(void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq, const void* Bq,
-                             const float* inv_sa, const float* inv_sb, hipStream_t s) {
-    static const hipError_t attr = hipFuncSetAttribute((const void*)k_gemm_update<OP, ST>,
-                                                       hipFuncAttributeMaxDynamicSharedMemorySize, gemm_lds_bytes());
+int gemm_tile_rows(int tile) { return tile == GEMM_TILE_128 ? 128 : 256; }
+
+template <int OP, int ST, int TMv>
+static hipError_t gemm_typed(const GemmCall* calls, int count, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_gemm_update<OP, ST, TMv>,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       gemm_lds_bytes<TMv>());
     if (attr) return attr;
-    const int tm = (int)((M + TM - 1) / TM), tn = (int)((N + TN - 1) / TN);
-    const int nt = tm * tn;
-    const int per_xcd = (nt + 7) / 8;
-    // vectorised C access needs 16-byte aligned columns
-    const int vec_ok = ((ldc * (int64_t)sizeof(typename Store<ST>::T)) % 16 == 0 && (((uintptr_t)C) % 16) == 0) ? 1 : 0;
-    k_gemm_update<OP, ST><<<8 * per_xcd, 256, gemm_lds_bytes(), s>>>((typename Store<ST>::T*)C, ldc, M, N, K,
-                                                                (const char*)Aq, (const char*)Bq, inv_sa, inv_sb,
-                                                                tm, tn, per_xcd, vec_ok);
+    GemmGroup grp;
+    int total = 0, used = 0;
+    for (int i = 0; i < count; ++i) {
+        const GemmCall& c = calls[i];
+        if (c.M <= 0 || c.N <= 0) continue;
+        GemmOne& g = grp.g[used++];
+        g.C = c.C; g.ldc = c.ldc; g.M = c.M; g.N = c.N;
+        g.Aq = (const char*)c.Aq; g.Bq = (const char*)c.Bq; g.inv_sa = c.inv_sa; g.inv_sb = c.inv_sb;
+        g.K = c.K;
+        g.tiles_m = (int)((c.M + TMv - 1) / TMv);
+        g.tiles_n = (int)((c.N + TN - 1) / TN);
+        total += g.tiles_m * g.tiles_n;
+        g.tile_end = total;
+        // vectorised C access needs 16-byte aligned columns
+        g.vec_ok = ((c.ldc * (int64_t)sizeof(typename Store<ST>::T)) % 16 == 0 && (((uintptr_t)c.C) % 16) == 0) ? 1
+                                                                                                               : 0;
+        g.pad = 0;
+    }
+    if (!used) return hipSuccess;
+    grp.count = used;
+    grp.per_xcd = (total + 7) / 8;
+    k_gemm_update<OP, ST, TMv><<<8 * grp.per_xcd, 256, gemm_lds_bytes<TMv>(), s>>>(grp);
     return hipGetLastError();
 }
 
-hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq,
-                       const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s) {
-    if (M <= 0 || N <= 0) return hipSuccess;
-    if ((K * dtype_bytes(update)) % GBK) return hipErrorInvalidValue;
-#define GCASE(U, S) if (update == U && store == S) return gemm_typed<U, S>(C, ldc, M, N, K, Aq, Bq, inv_sa, inv_sb, s)
+hipError_t gemm_group(int update, int store, int tile, const GemmCall* calls, int count, hipStream_t s) {
+    if (count < 1 || count > GEMM_GROUP_MAX) return hipErrorInvalidValue;
+    for (int i = 0; i < count; ++i)
+        if ((calls[i].K * dtype_bytes(update)) % GBK) return hipErrorInvalidValue;
+#define GCASE(U, S)                                                                                      \
+    if (update == U && store == S)                                                                       \
+        return tile == GEMM_TILE_128 ? gemm_typed<U, S, 128>(calls, count, s) : gemm_typed<U, S, 256>(calls, count, s)
     GCASE(F32, F32);
     GCASE(F16, F16);
     GCASE(BF16, BF16);
@@ -385,6 +441,13 @@ hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, i
     GCASE(BF16, F32);
 #undef GCASE
     return hipErrorInvalidValue;
+}
+
+hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq,
+                       const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s, int tile) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    GemmCall c{C, ldc, M, N, K, Aq, Bq, inv_sa, inv_sb};
+    return gemm_group(update, store, tile, &c, 1, s);
 }
 
 }  // namespace mxp

@@ -27,11 +27,13 @@ hipError_t fill_u64(void* p, int64_t count, uint64_t v, hipStream_t s) {
 // Thread (row i, column quad q): one Philox call gives A[i, 4q..4q+3].
 // Each thread also accumulates sum_j |k(i,j) - 2^31| exactly in 64-bit
 // integers; the per-row sums are combined with integer atomics, which are
-// exact and order independent.
+// exact and order independent.  Entries are s 2^-32 (s = k - 2^31) for the
+// matrices with entries in [-1/2, 1/2), s 2^-31 for those in [-1, 1).
 constexpr int GEN_QUADS = 64;  // column quads per thread
 
 template <int ST>
-__global__ __launch_bounds__(256) void k_gen_matrix(int64_t n, uint64_t seed, typename Store<ST>::T* A, int64_t lda,
+__global__ __launch_bounds__(256) void k_gen_matrix(int64_t n, uint64_t seed, double scale,
+                                                    typename Store<ST>::T* A, int64_t lda,
                                                     unsigned long long* rowsum) {
     uint32_t k0[10], k1[10];
     philox_keys(seed, k0, k1);
@@ -50,18 +52,26 @@ __global__ __launch_bounds__(256) void k_gen_matrix(int64_t n, uint64_t seed, ty
             if (j < n) {
                 int32_t s = draw_offset(w[t]);
                 acc += (unsigned long long)(s < 0 ? -(int64_t)s : (int64_t)s);
-                if (A) A[i + j * lda] = Store<ST>::from_f64((double)s * 0x1p-32);
+                if (A) A[i + j * lda] = Store<ST>::from_f64((double)s * scale);
             }
         }
     }
     atomicAdd(&rowsum[i], acc);
 }
 
-// diag[i] = rowsum * 2^-32 (exact), A[i,i] = RNE(diag[i]); ||A||_inf via an
-// integer max of 2*rowsum - |own draw| (the off-diagonal sum plus the diagonal)
+// The diagonal and the row 1-norms from the integer row sums S (held in the
+// diag array until here) and the row's own draw s_ii:
+//   dominant: A_ii = S 2^-32 (the whole row's |draws|, own one included),
+//             ||A_i||_1 = (2S - |s_ii|) 2^-32;
+//   sqrt(n):  A_ii = s_ii 2^-32 + shift (shift = gamma sqrt(n), formed on the
+//             host), ||A_i||_1 = (S - |s_ii|) 2^-32 + |A_ii|;
+//   uniform:  A_ii = s_ii 2^-31, ||A_i||_1 = S 2^-31.
+// ||A||_inf is the largest row norm: a maximum over the bit patterns of
+// non-negative doubles, which order like the values.
 template <int ST>
-__global__ __launch_bounds__(256) void k_gen_finalize(int64_t n, uint64_t seed, typename Store<ST>::T* A, int64_t lda,
-                                                      double* diag, unsigned long long* amax) {
+__global__ __launch_bounds__(256) void k_gen_finalize(int64_t n, uint64_t seed, int kind, double shift,
+                                                      typename Store<ST>::T* A, int64_t lda, double* diag,
+                                                      double* row_l1, unsigned long long* amax) {
     uint32_t k0[10], k1[10];
     philox_keys(seed, k0, k1);
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -71,15 +81,26 @@ __global__ __launch_bounds__(256) void k_gen_finalize(int64_t n, uint64_t seed, 
     philox4((uint32_t)i, (uint32_t)(i >> 2), 0u, k0, k1, w);
     int32_t s = draw_offset(w[i & 3]);
     unsigned long long own = (unsigned long long)(s < 0 ? -(int64_t)s : (int64_t)s);
-    double d = (double)S * 0x1p-32;
+    double d, l1;
+    if (kind == 1) {
+        d = (double)s * 0x1p-32 + shift;
+        l1 = (double)(S - own) * 0x1p-32 + fabs(d);
+    } else if (kind == 2) {
+        d = (double)s * 0x1p-31;
+        l1 = (double)S * 0x1p-31;
+    } else {
+        d = (double)S * 0x1p-32;
+        l1 = (double)(2ull * S - own) * 0x1p-32;
+    }
     diag[i] = d;
+    if (row_l1) row_l1[i] = l1;
     if (A) A[i + i * lda] = Store<ST>::from_f64(d);
-    atomicMax(amax, 2ull * S - own);
+    atomicMax(amax, (unsigned long long)__double_as_longlong(l1));
 }
 
 __global__ void k_gen_anorm(double* a_inf) {
     unsigned long long m = *(unsigned long long*)a_inf;
-    *a_inf = (double)m * 0x1p-32;
+    *a_inf = __longlong_as_double((long long)m);
 }
 
 __global__ __launch_bounds__(256) void k_gen_rhs(int64_t n, int64_t nrhs, uint64_t seed, double* B, int64_t ldb) {
@@ -97,17 +118,20 @@ __global__ __launch_bounds__(256) void k_gen_rhs(int64_t n, int64_t nrhs, uint64
     }
 }
 
+double gen_offscale(int kind) { return kind == 2 ? 0x1p-31 : 0x1p-32; }
+
 template <int ST>
-static hipError_t gen_launch(int64_t n, int64_t nrhs, uint64_t seed, void* A, int64_t lda, double* B, int64_t ldb,
-                             double* diag, double* a_inf, hipStream_t s) {
+static hipError_t gen_launch(int64_t n, int64_t nrhs, uint64_t seed, int kind, double shift, void* A, int64_t lda,
+                             double* B, int64_t ldb, double* diag, double* row_l1, double* a_inf, hipStream_t s) {
     typedef typename Store<ST>::T T;
     hipError_t e;
     if ((e = fill_u64(diag, n, 0, s))) return e;
     if ((e = fill_u64(a_inf, 1, 0, s))) return e;
     dim3 g((unsigned)((n + 255) / 256), (unsigned)(((n + 3) / 4 + GEN_QUADS - 1) / GEN_QUADS));
-    k_gen_matrix<ST><<<g, dim3(256), 0, s>>>(n, seed, (T*)A, lda, (unsigned long long*)diag);
+    k_gen_matrix<ST><<<g, dim3(256), 0, s>>>(n, seed, gen_offscale(kind), (T*)A, lda, (unsigned long long*)diag);
     if ((e = hipGetLastError())) return e;
-    k_gen_finalize<ST><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, seed, (T*)A, lda, diag,
+    k_gen_finalize<ST><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s>>>(n, seed, kind, shift, (T*)A, lda,
+                                                                               diag, row_l1,
                                                                                (unsigned long long*)a_inf);
     if ((e = hipGetLastError())) return e;
     k_gen_anorm<<<1, 1, 0, s>>>(a_inf);
@@ -119,13 +143,13 @@ static hipError_t gen_launch(int64_t n, int64_t nrhs, uint64_t seed, void* A, in
     return hipSuccess;
 }
 
-hipError_t generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void* A, int64_t lda, double* B, int64_t ldb,
-                    double* diag, double* a_inf, hipStream_t s) {
+hipError_t generate(int64_t n, int64_t nrhs, uint64_t seed, int kind, double shift, int store, void* A, int64_t lda,
+                    double* B, int64_t ldb, double* diag, double* row_l1, double* a_inf, hipStream_t s) {
     switch (store) {
-    case F64: return gen_launch<F64>(n, nrhs, seed, A, lda, B, ldb, diag, a_inf, s);
-    case F32: return gen_launch<F32>(n, nrhs, seed, A, lda, B, ldb, diag, a_inf, s);
-    case F16: return gen_launch<F16>(n, nrhs, seed, A, lda, B, ldb, diag, a_inf, s);
-    case BF16: return gen_launch<BF16>(n, nrhs, seed, A, lda, B, ldb, diag, a_inf, s);
+    case F64: return gen_launch<F64>(n, nrhs, seed, kind, shift, A, lda, B, ldb, diag, row_l1, a_inf, s);
+    case F32: return gen_launch<F32>(n, nrhs, seed, kind, shift, A, lda, B, ldb, diag, row_l1, a_inf, s);
+    case F16: return gen_launch<F16>(n, nrhs, seed, kind, shift, A, lda, B, ldb, diag, row_l1, a_inf, s);
+    case BF16: return gen_launch<BF16>(n, nrhs, seed, kind, shift, A, lda, B, ldb, diag, row_l1, a_inf, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -135,7 +159,8 @@ hipError_t generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void* A, 
 // of A[i,j] * X[j,r], with A[i,j] regenerated.  A thread owns one row; all
 // threads of a wave walk the same columns, so X[j,r] is a wave-uniform load.
 // The sums are taken over the integer draws s (A[i,j] = s 2^-32) and scaled
-// by 2^-32 once at the end: scaling by a power of two commutes with every
+// by the power of two of the matrix kind (2^-32, or 2^-31 for entries in
+// [-1, 1)) once at the end: scaling by a power of two commutes with every
 // rounding, so the result is that of summing the draws' values.  The sign
 // flip of the draws (s = word ^ 2^31) is folded into the last round keys for
 // words 0 and 2, which leave the last round xor-ed with them (the caller
@@ -175,7 +200,8 @@ MXP_DEV void regen_cols(uint32_t row, int64_t i, int64_t j0, int64_t j1, const u
 }
 
 template <int NR>
-__global__ __launch_bounds__(256) void k_regen_gemv(int64_t n, uint64_t seed, const double* __restrict__ X, int64_t ldx,
+__global__ __launch_bounds__(256) void k_regen_gemv(int64_t n, uint64_t seed, double offscale,
+                                                    const double* __restrict__ X, int64_t ldx,
                                                     double* __restrict__ P, int64_t chunk_cols) {
     uint32_t k0[10], k1[10];
     philox_keys(seed, k0, k1);
@@ -193,7 +219,7 @@ __global__ __launch_bounds__(256) void k_regen_gemv(int64_t n, uint64_t seed, co
     else regen_cols<NR, false>(row, i, j0, j1, k0, k1, X, ldx, acc);
     if (i < n) {
 #pragma unroll
-        for (int r = 0; r < NR; ++r) P[((int64_t)blockIdx.y * NR + r) * n + i] = acc[r] * 0x1p-32;
+        for (int r = 0; r < NR; ++r) P[((int64_t)blockIdx.y * NR + r) * n + i] = acc[r] * offscale;
     }
 }
 
@@ -228,8 +254,9 @@ size_t regen_partial_bytes(int64_t n, int nr) {
     return (size_t)nchunk * nr * n * sizeof(double);
 }
 
-hipError_t regen_matvec(int64_t n, uint64_t seed, const double* diag, const double* X, int64_t ldx, int nr,
+hipError_t regen_matvec(int64_t n, uint64_t seed, int kind, const double* diag, const double* X, int64_t ldx, int nr,
                         const double* B, int64_t ldb, double* R, int64_t ldr, double* P, hipStream_t s) {
+    const double osc = gen_offscale(kind);
     int64_t cc = regen_chunk_cols(n);
     int64_t nchunk = (n + cc - 1) / cc;
     dim3 g((unsigned)((n + 255) / 256), (unsigned)nchunk);
@@ -239,10 +266,10 @@ hipError_t regen_matvec(int64_t n, uint64_t seed, const double* diag, const doub
         int left = nr - r0;
         int w = left >= 8 ? 8 : left >= 4 ? 4 : left >= 2 ? 2 : 1;
         switch (w) {
-        case 8: k_regen_gemv<8><<<g, dim3(256), 0, s>>>(n, seed, X + r0 * ldx, ldx, P, cc); break;
-        case 4: k_regen_gemv<4><<<g, dim3(256), 0, s>>>(n, seed, X + r0 * ldx, ldx, P, cc); break;
-        case 2: k_regen_gemv<2><<<g, dim3(256), 0, s>>>(n, seed, X + r0 * ldx, ldx, P, cc); break;
-        default: k_regen_gemv<1><<<g, dim3(256), 0, s>>>(n, seed, X + r0 * ldx, ldx, P, cc); break;
+        case 8: k_regen_gemv<8><<<g, dim3(256), 0, s>>>(n, seed, osc, X + r0 * ldx, ldx, P, cc); break;
+        case 4: k_regen_gemv<4><<<g, dim3(256), 0, s>>>(n, seed, osc, X + r0 * ldx, ldx, P, cc); break;
+        case 2: k_regen_gemv<2><<<g, dim3(256), 0, s>>>(n, seed, osc, X + r0 * ldx, ldx, P, cc); break;
+        default: k_regen_gemv<1><<<g, dim3(256), 0, s>>>(n, seed, osc, X + r0 * ldx, ldx, P, cc); break;
         }
         hipError_t e = hipGetLastError();
         if (e) return e;
@@ -256,11 +283,19 @@ hipError_t regen_matvec(int64_t n, uint64_t seed, const double* diag, const doub
 }
 
 // ---------------------------------------------------------------- norms
-// Per-block maxima of |r|, |x|, |b| (three columns of partials), then one
-// block forms eta = ||r|| / ((||A|| ||x|| + ||b||) n 2^-53).
-__global__ __launch_bounds__(256) void k_absmax3(int64_t n, const double* __restrict__ r, const double* __restrict__ x,
-                                                 const double* __restrict__ b, double* __restrict__ part) {
+// Per-block maxima of |r|, |x|, |b| (three columns of partials) for each
+// right-hand side q = blockIdx.y, then one block per right-hand side forms
+// eta = ||r|| / ((||A|| ||x|| + ||b||) n 2^-53).
+__global__ __launch_bounds__(256) void k_absmax3(int64_t n, const double* __restrict__ r, int64_t ldr,
+                                                 const double* __restrict__ x, int64_t ldx,
+                                                 const double* __restrict__ b, int64_t ldb,
+                                                 double* __restrict__ part) {
     __shared__ double red[3][4];
+    const int q = blockIdx.y;
+    r += q * ldr;
+    x += q * ldx;
+    b += q * ldb;
+    part += (int64_t)q * gridDim.x * 3;
     double mr = 0, mx = 0, mb = 0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         mr = fmax(mr, fabs(r[i]));
@@ -277,9 +312,12 @@ __global__ __launch_bounds__(256) void k_absmax3(int64_t n, const double* __rest
     }
 }
 
+// eta_out[4 q .. 4 q + 2] = (eta, ||x||_inf, ||r||_inf) of right-hand side q
 __global__ void k_eta_final(int64_t n, int nblk, const double* __restrict__ part, const double* __restrict__ a_inf,
                             double* __restrict__ eta_out) {
     __shared__ double red[3][4];
+    const int q = blockIdx.x;
+    part += (int64_t)q * nblk * 3;
     double mr = 0, mx = 0, mb = 0;
     for (int i = threadIdx.x; i < nblk; i += 256) {
         mr = fmax(mr, part[i * 3 + 0]);
@@ -292,11 +330,11 @@ __global__ void k_eta_final(int64_t n, int nblk, const double* __restrict__ part
     __syncthreads();
     if (threadIdx.x == 0) {
         double R = 0, Xn = 0, Bn = 0;
-        for (int q = 0; q < 4; ++q) { R = fmax(R, red[0][q]); Xn = fmax(Xn, red[1][q]); Bn = fmax(Bn, red[2][q]); }
+        for (int k = 0; k < 4; ++k) { R = fmax(R, red[0][k]); Xn = fmax(Xn, red[1][k]); Bn = fmax(Bn, red[2][k]); }
         double den = (a_inf[0] * Xn + Bn) * (double)n * 0x1p-53;
-        eta_out[0] = R / den;
-        eta_out[1] = Xn;
-        eta_out[2] = R;
+        eta_out[4 * q] = R / den;
+        eta_out[4 * q + 1] = Xn;
+        eta_out[4 * q + 2] = R;
     }
 }
 
@@ -307,13 +345,14 @@ int eta_blocks(int64_t n) {
     return (int)b;
 }
 
-hipError_t hpl_eta_dev(int64_t n, const double* r, const double* x, const double* b, const double* a_inf,
-                       double* part, double* eta_out, hipStream_t s) {
+hipError_t hpl_eta_dev(int64_t n, int nr, const double* r, int64_t ldr, const double* x, int64_t ldx,
+                       const double* b, int64_t ldb, const double* a_inf, double* part, double* eta_out,
+                       hipStream_t s) {
     int nb = eta_blocks(n);
-    k_absmax3<<<dim3(nb), dim3(256), 0, s>>>(n, r, x, b, part);
+    k_absmax3<<<dim3(nb, nr), dim3(256), 0, s>>>(n, r, ldr, x, ldx, b, ldb, part);
     hipError_t e = hipGetLastError();
     if (e) return e;
-    k_eta_final<<<1, 256, 0, s>>>(n, nb, part, a_inf, eta_out);
+    k_eta_final<<<nr, 256, 0, s>>>(n, nb, part, a_inf, eta_out);
     return hipGetLastError();
 }
 

@@ -7,15 +7,22 @@ namespace mxp {
 
 // ---- generation / residual (gen.hip)
 hipError_t fill_u64(void* p, int64_t count, uint64_t v, hipStream_t s);
-hipError_t generate(int64_t n, int64_t nrhs, uint64_t seed, int store, void* A, int64_t lda, double* B, int64_t ldb,
-                    double* diag, double* a_inf, hipStream_t s);
+// kind: 0 diagonally dominant, 1 diagonal gamma sqrt(n) (shift = gamma sqrt(n)),
+// 2 uniform in [-1, 1) without diagonal change
+hipError_t generate(int64_t n, int64_t nrhs, uint64_t seed, int kind, double shift, int store, void* A, int64_t lda,
+                    double* B, int64_t ldb, double* diag, double* row_l1, double* a_inf, hipStream_t s);
+// value of one unit of a draw offset k - 2^31 in the matrix of a kind
+double gen_offscale(int kind);
 int64_t regen_chunk_cols(int64_t n);
 size_t regen_partial_bytes(int64_t n, int nr);
-hipError_t regen_matvec(int64_t n, uint64_t seed, const double* diag, const double* X, int64_t ldx, int nr,
+hipError_t regen_matvec(int64_t n, uint64_t seed, int kind, const double* diag, const double* X, int64_t ldx, int nr,
                         const double* B, int64_t ldb, double* R, int64_t ldr, double* P, hipStream_t s);
 int eta_blocks(int64_t n);
-hipError_t hpl_eta_dev(int64_t n, const double* r, const double* x, const double* b, const double* a_inf,
-                       double* part, double* eta_out, hipStream_t s);
+// eta_out[4 q] = HPL scaled residual of right-hand side q (q < nr), [4 q + 1]
+// ||x_q||_inf, [4 q + 2] ||r_q||_inf; part: eta_blocks(n) * 3 * nr doubles
+hipError_t hpl_eta_dev(int64_t n, int nr, const double* r, int64_t ldr, const double* x, int64_t ldx,
+                       const double* b, int64_t ldb, const double* a_inf, double* part, double* eta_out,
+                       hipStream_t s);
 
 // ---- factorisation (lu.hip)
 struct FactorPlan {
@@ -39,6 +46,7 @@ struct FactorPlan {
     float* inv_sb;   // 2 sets of op_rows/32
     unsigned long long* info;  // 1
     int* dsync;      // nblk x diag_sync_words(): phase counters of the diagonal-block LUs (zeroed per factorisation)
+    int gemm_tile = 0;  // work-group tile of the trailing update (GEMM_TILE_*)
 };
 
 struct AuxLayout {
@@ -52,9 +60,25 @@ int64_t operand_rows(int64_t n);
 WorkLayout work_layout(int64_t n, int64_t nb, int update);
 int dtype_bytes(int dt);
 
-// C (M x N, storage) <- C - diag(inv_sa) Aq Bq^T diag(inv_sb); Aq/Bq rows padded to 256
+// C (M x N, storage) <- C - diag(inv_sa) Aq Bq^T diag(inv_sb); Aq/Bq rows padded to 256.
+// tile: the work-group tile of the update kernel (256 x 128 or 128 x 128).
+enum { GEMM_TILE_256 = 0, GEMM_TILE_128 = 1 };
+constexpr int GEMM_GROUP_MAX = 8;
+struct GemmCall {
+    void* C;
+    int64_t ldc, M, N;
+    int K;
+    const void* Aq;
+    const void* Bq;
+    const float* inv_sa;
+    const float* inv_sb;
+};
+int gemm_tile_rows(int tile);
 hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq,
-                       const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s);
+                       const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s,
+                       int tile = GEMM_TILE_256);
+// up to GEMM_GROUP_MAX independent updates (same formats and tile) in one launch
+hipError_t gemm_group(int update, int store, int tile, const GemmCall* calls, int count, hipStream_t s);
 // FP32 LU of the diagonal block A[k:k+kb, k:k+kb] (padded to kbp, a multiple
 // of 64, with the identity) by a few cooperating work-groups: T/Trm (ld ldt)
 // get L\U column- and row-major, linv/uinv the 64x64 sub-block inverses, A
@@ -62,6 +86,16 @@ hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, i
 // zero / non-finite pivot sets *info (atomic min) to its 1-based column; an
 // expired wait sets it to 2^62.
 size_t diag_sync_words();
+struct DiagCall {
+    void* A;
+    int64_t lda, k;
+    int kb, kbp, ldt;
+    float *T, *Trm, *linv, *uinv;
+    int* sync;
+    unsigned long long* info;
+};
+// the diagonal-block LUs of up to GEMM_GROUP_MAX factorisations in one launch
+hipError_t diag_lu_group(int store, const DiagCall* calls, int count, hipStream_t s);
 hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
                    float* linv, float* uinv, int* sync, unsigned long long* info, hipStream_t s);
 hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t s);
@@ -78,9 +112,24 @@ struct Lookahead {
 hipError_t lookahead_create(Lookahead* la);
 void lookahead_destroy(Lookahead* la);
 hipError_t factor_run(const FactorPlan& p, hipStream_t s, Lookahead* la = nullptr);
+// up to GEMM_GROUP_MAX factorisations (same formats, any sizes) in lockstep on
+// one stream: per block step one launch each of the diagonal-block LUs, the
+// strip TRSMs and the trailing updates of all of them (no look-ahead)
+hipError_t factor_group(const FactorPlan* plans, int count, hipStream_t s);
 // mxp_factor with an explicit look-ahead context (api.hip)
 int factor_with(int64_t n, int64_t nb, int update, int store, int scaling, const double* diag, void* A, int64_t lda,
                 void* aux, void* work, size_t work_bytes, int64_t* info, hipStream_t s, Lookahead* la);
+
+// ---- FP64 LU with or without partial pivoting (lu64.hip)
+int lu64_block(int64_t n);
+size_t lu64_work_bytes(int64_t n);
+int* lu64_err_word(void* work, int64_t n);
+hipError_t lu64_factor(int64_t n, double* A, int64_t lda, int64_t* ipiv, void* work, unsigned long long* info_dev,
+                       int use_rocblas, hipStream_t s);
+hipError_t lu64_solve(int64_t n, const double* A, int64_t lda, const int64_t* ipiv, double* X, int64_t ldx, int nr,
+                      hipStream_t s);
+hipError_t gemm64(double* C, int64_t ldc, const double* A, int64_t lda, const double* B, int64_t ldb, int64_t M,
+                  int64_t N, int K, hipStream_t s);
 
 // ---- preconditioner and GMRES pieces (solve.hip)
 struct PrecPlan {
@@ -104,14 +153,22 @@ hipError_t prec_apply(const PrecPlan& p, const double* V, int64_t ldv, double* Z
 hipError_t prec_err_reset(double* W, int64_t n, int nr, hipStream_t s);
 hipError_t prec_err_read(double* W, int64_t n, int nr, int* err, hipStream_t s);
 
-hipError_t mgs_step(int64_t n, const double* V, int k, double* w, double* hcol, double* part, hipStream_t s);
-hipError_t norm_normalize(int64_t n, double* w, double* vout, double* hsub, double* part, hipStream_t s);
-hipError_t givens_step(int k, double* H, int ldh, double* cs, double* sn, double* g, const double* xnorm, double tau,
-                       double* flag, hipStream_t s);
-hipError_t lsq_update(int64_t n, int k, const double* H, int ldh, const double* g, double* y, const double* V,
-                      double* x, hipStream_t s);
-hipError_t vec_norm2(int64_t n, const double* x, double* out, double* part, hipStream_t s);
-hipError_t vec_scale_copy(int64_t n, const double* x, const double* beta, double* v, double* g0, hipStream_t s);
+// GMRES steps for nr right-hand sides in lockstep (solve.hip).  V holds the
+// bases, v_{r,j} at V + (j nr + r) n; W the new vectors (n x nr); H, cs, sn,
+// g, y per right-hand side with ldh = m + 1 (H: ldh x m each); part: 2 x nr x
+// 256 partial sums; act[r]: right-hand side r takes part; sc: per-r scalars
+// with stride sc_stride.
+hipError_t gm_norms(int64_t n, int nr, const double* X, int64_t ldx, double* out, int out_stride, double* part,
+                    const int* act, hipStream_t s);
+hipError_t gm_start(int64_t n, int nr, const double* Z, const double* sc, int sc_stride, double* V, double* g,
+                    int ldg, const int* act, hipStream_t s);
+hipError_t gm_arnoldi(int64_t n, int nr, double* V, int k, double* W, double* part, double* H, int ldh,
+                      const int* act, hipStream_t s);
+hipError_t gm_givens(int nr, int k, double* H, int ldh, double* cs, double* sn, double* g, const double* sc,
+                     int sc_stride, double tau, int* flag, const int* act, hipStream_t s);
+hipError_t gm_update(int64_t n, int nr, const double* H, int ldh, const double* g, double* y, const int* kdim,
+                     const double* V, double* X, int64_t ldx, hipStream_t s);
+hipError_t set_i32(int* dst, int n, const int* src_dev, hipStream_t s);
 int red_blocks(int64_t n);
 
 }  // namespace mxp

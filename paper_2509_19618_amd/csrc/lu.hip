@@ -14,6 +14,7 @@
 //   3. A22 <- A22 - L21 U12 on the matrix cores (MFMA), FP32 accumulation,
 //      result rounded to the storage format.
 #include <mutex>
+#include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -70,18 +71,22 @@ WorkLayout work_layout(int64_t n, int64_t nb, int update) {
 }
 
 // ============================================================== scaling
-// Row equilibration: S_ii = 2^-p with 2^p the power of two nearest the
-// diagonal (the largest entry of its row); A <- S A in place (exact except
-// where a value drops into the subnormal range of the storage format).
+// Row equilibration: S_ii = 2^(t - p) with 2^p the power of two nearest the
+// diagonal (the largest entry of its row), so the diagonal lands near 2^t;
+// A <- S A in place, exactly.  t = 14 for FP16 storage, whose normal range
+// ends below 2^-14: with the diagonal near 1 the off-diagonal entries (about
+// n/4 times smaller) would be stored as subnormals, with the diagonal near
+// 2^14 they stay normal; t = 0 for BF16 and FP32 storage.
 template <int ST>
 __global__ __launch_bounds__(256) void k_row_scale(int64_t n, typename Store<ST>::T* A, int64_t lda,
-                                                   const double* __restrict__ diag, double* __restrict__ rowscale) {
+                                                   const double* __restrict__ diag, double* __restrict__ rowscale,
+                                                   int target) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     int e;
     double f = frexp(diag[i], &e);        // diag = f 2^e, f in [0.5, 1)
     int p = (f < 0.70710678118654752) ? e - 1 : e;
-    double S = ldexp(1.0, -p);
+    double S = ldexp(1.0, target - p);
     if (blockIdx.y == 0) rowscale[i] = S;
     float Sf = (float)S;
     int64_t j0 = (int64_t)blockIdx.y * 64;
@@ -100,9 +105,9 @@ __global__ void k_fill_f64(double* p, int64_t n, double v) {
 hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t s) {
     dim3 g((unsigned)((p.n + 255) / 256), (unsigned)((p.n + 63) / 64));
     switch (p.store) {
-    case F32: k_row_scale<F32><<<g, 256, 0, s>>>(p.n, (float*)p.A, p.lda, diag, p.rowscale); break;
-    case F16: k_row_scale<F16><<<g, 256, 0, s>>>(p.n, (half_t*)p.A, p.lda, diag, p.rowscale); break;
-    case BF16: k_row_scale<BF16><<<g, 256, 0, s>>>(p.n, (bf16_t*)p.A, p.lda, diag, p.rowscale); break;
+    case F32: k_row_scale<F32><<<g, 256, 0, s>>>(p.n, (float*)p.A, p.lda, diag, p.rowscale, 0); break;
+    case F16: k_row_scale<F16><<<g, 256, 0, s>>>(p.n, (half_t*)p.A, p.lda, diag, p.rowscale, 14); break;
+    case BF16: k_row_scale<BF16><<<g, 256, 0, s>>>(p.n, (bf16_t*)p.A, p.lda, diag, p.rowscale, 0); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -417,17 +422,39 @@ MXP_DEV void trsm_U_strip(typename Store<ST>::T* A, int64_t lda, int64_t n, int6
 }
 
 // Both strip solves of one block step in one launch: work-groups [0, nstrip)
-// solve the L21 strips, [nstrip, 2 nstrip) the U12 strips (independent).
+// solve the L21 strips, [nstrip, 2 nstrip) the U12 strips (independent).  One
+// launch serves a group of factorisations (one per request of the solve
+// server, or a single one): their work-groups are numbered one after another.
+struct TrsmOne {
+    void* A;
+    int64_t lda, n, k;
+    int nb, nstrip, wg_end, pad;
+    const float *Urm, *uinv, *T, *linv;
+    void* Lq;
+    float* inv_sa;
+    float* lsc_blk;
+    void* Uq;
+    float* inv_sb;
+};
+struct TrsmGroup {
+    TrsmOne g[GEMM_GROUP_MAX];
+    int count;
+};
+
 template <int ST, int OP>
-__global__ __launch_bounds__(256) void k_trsm(typename Store<ST>::T* A, int64_t lda, int64_t n, int64_t k, int nb,
-                                              int nstrip, const float* __restrict__ Urm, const float* __restrict__ uinv,
-                                              const float* __restrict__ T, const float* __restrict__ linv,
-                                              typename Operand<OP>::T* Lq, float* inv_sa, float* lsc_blk,
-                                              typename Operand<OP>::T* Uq, float* inv_sb) {
+__global__ __launch_bounds__(256) void k_trsm(const TrsmGroup grp) {
     extern __shared__ float smem[];
-    const int w = (int)blockIdx.x;
-    if (w < nstrip) trsm_L_strip<ST, OP>(A, lda, n, k, nb, Urm, uinv, Lq, inv_sa, lsc_blk, smem, w);
-    else trsm_U_strip<ST, OP>(A, lda, n, k, nb, T, linv, Uq, inv_sb, smem, w - nstrip);
+    int d = 0;
+    while ((int)blockIdx.x >= grp.g[d].wg_end) ++d;
+    const TrsmOne& G = grp.g[d];
+    const int w = (int)blockIdx.x - (d > 0 ? grp.g[d - 1].wg_end : 0);
+    typename Store<ST>::T* A = (typename Store<ST>::T*)G.A;
+    if (w < G.nstrip)
+        trsm_L_strip<ST, OP>(A, G.lda, G.n, G.k, G.nb, G.Urm, G.uinv, (typename Operand<OP>::T*)G.Lq, G.inv_sa,
+                             G.lsc_blk, smem, w);
+    else
+        trsm_U_strip<ST, OP>(A, G.lda, G.n, G.k, G.nb, G.T, G.linv, (typename Operand<OP>::T*)G.Uq, G.inv_sb, smem,
+                             w - G.nstrip);
 }
 
 // Full inverses of the diagonal blocks (for the preconditioner), all blocks
@@ -501,21 +528,65 @@ void lookahead_destroy(Lookahead* la) {
     *la = Lookahead();
 }
 
-// The look-ahead context of callers that bring none: one per device (default
-// stream priority; created on first use and kept for the process).
-static Lookahead g_la[64];
+// Look-ahead contexts of callers that bring none: a pool per device
+// (default stream priority).  A call takes a context for the time it
+// enqueues its work and returns it afterwards; work still in flight on the
+// context's side stream is no hazard for the next user, whose waits and
+// records are enqueued after it (a wait on an event refers to the event's
+// latest record at the time of the wait call).  Two calls never enqueue on
+// one context at the same time.
+static std::vector<Lookahead*> g_la_free[64];
 static std::mutex g_la_mutex;
 
-static hipError_t lookahead_for_device(Lookahead** out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e) return e;
-    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-    std::lock_guard<std::mutex> lock(g_la_mutex);
-    Lookahead& L = g_la[dev];
-    if (!L.side && (e = lookahead_create(&L))) return e;
-    *out = &L;
+static hipError_t lookahead_acquire(int dev, Lookahead** out) {
+    {
+        std::lock_guard<std::mutex> lock(g_la_mutex);
+        if (!g_la_free[dev].empty()) {
+            *out = g_la_free[dev].back();
+            g_la_free[dev].pop_back();
+            return hipSuccess;
+        }
+    }
+    Lookahead* L = new Lookahead();
+    hipError_t e = lookahead_create(L);
+    if (e) {
+        lookahead_destroy(L);
+        delete L;
+        return e;
+    }
+    *out = L;
     return hipSuccess;
+}
+
+static void lookahead_release(int dev, Lookahead* L) {
+    std::lock_guard<std::mutex> lock(g_la_mutex);
+    g_la_free[dev].push_back(L);
+}
+
+// the strip-TRSM descriptor of block step k of a factorisation; wg_begin: the
+// work-groups of the group before it
+template <int ST, int OP>
+static void trsm_desc(const FactorPlan& p, int64_t k, TrsmOne& g, int wg_begin) {
+    typedef typename Operand<OP>::T OP_T;
+    const int nb = (int)p.nb;
+    const int kb = (int)(p.n - k < nb ? p.n - k : nb);
+    const int64_t m = p.n - k - kb;
+    const int64_t blk = k / nb;
+    const int set = (int)(blk & 1);
+    const int64_t opset = p.op_rows * nb, scset = p.op_rows / 32;
+    const int nstrip = (int)(rup(m, 256) / SR);
+    g.A = p.A; g.lda = p.lda; g.n = p.n; g.k = k; g.nb = nb; g.nstrip = nstrip;
+    g.wg_end = wg_begin + 2 * nstrip;
+    g.pad = 0;
+    g.Urm = p.Trm + blk * nb * nb;
+    g.uinv = p.uinv + blk * nb * 64;
+    g.T = p.T + blk * nb * nb;
+    g.linv = p.linv + blk * nb * 64;
+    g.Lq = (OP_T*)p.Lq + set * opset;
+    g.inv_sa = p.inv_sa + set * scset;
+    g.lsc_blk = p.lsc + blk * ((p.n + SR - 1) / SR);
+    g.Uq = (OP_T*)p.Uq + set * opset;
+    g.inv_sb = p.inv_sb + set * scset;
 }
 
 // Right-looking blocked LU with look-ahead.  Per block step k the trailing
@@ -545,11 +616,9 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     if (attr) return attr;
     hipError_t e;
     Lookahead* LA = la;
-    if (!LA && (e = lookahead_for_device(&LA))) return e;
     ST_T* A = (ST_T*)p.A;
     const int64_t n = p.n, lda = p.lda;
     const int nb = (int)p.nb;
-    const int64_t nstrips_total = (n + SR - 1) / SR;
     const int64_t opset = p.op_rows * nb;            // elements of one operand buffer
     const int64_t scset = p.op_rows / 32;             // entries of one scale array
 
@@ -573,16 +642,11 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         const int kb = (int)(n - k < nb ? n - k : nb);
         const int64_t m = n - k - kb;
         if (m <= 0) return hipSuccess;
-        const int64_t blk = k / nb;
-        const int set = (int)(blk & 1);
-        const int nstrip = (int)(rup(m, 256) / SR);
-        const size_t smem = trsm_smem(nb);
+        TrsmGroup grp;
+        trsm_desc<ST, OP>(p, k, grp.g[0], 0);
+        grp.count = 1;
         hipEvent_t pt = prof::begin(prof::TRSM, st);
-        k_trsm<ST, OP><<<2 * nstrip, 256, smem, st>>>(A, lda, n, k, nb, nstrip, p.Trm + blk * nb * nb,
-                                                       p.uinv + blk * nb * 64, p.T + blk * nb * nb,
-                                                       p.linv + blk * nb * 64, (OP_T*)p.Lq + set * opset,
-                                                       p.inv_sa + set * scset, p.lsc + blk * nstrips_total,
-                                                       (OP_T*)p.Uq + set * opset, p.inv_sb + set * scset);
+        k_trsm<ST, OP><<<grp.g[0].wg_end, 256, trsm_smem(nb), st>>>(grp);
         prof::end(pt, prof::TRSM, st, 2.0 * m * (double)nb * nb,
                   4.0 * m * (double)nb * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
         return hipGetLastError();
@@ -598,7 +662,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         ST_T* C = A + (k + nb + c0) + (k + nb + c1) * lda;
         hipEvent_t pt = prof::begin(prof::GEMM, st);
         hipError_t e2 = gemm_update(OP, ST, C, lda, M, N, nb, Lq + c0 * nb, Uq + c1 * nb, sa + c0 / 32, sb + c1 / 32,
-                                    st);
+                                    st, p.gemm_tile);
         prof::end(pt, prof::GEMM, st, 2.0 * M * (double)N * nb,
                   2.0 * M * (double)N * sizeof(ST_T) + (M + N) * (double)nb * sizeof(OP_T));
         return e2;
@@ -665,7 +729,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     return hipSuccess;
 }
 
-hipError_t factor_run(const FactorPlan& p, hipStream_t s, Lookahead* la) {
+static hipError_t factor_dispatch(const FactorPlan& p, hipStream_t s, Lookahead* la) {
     const int u = p.update, t = p.store;
     if (u == F32 && t == F32) return factor_typed<F32, F32>(p, s, la);
     if (u == F16 && t == F16) return factor_typed<F16, F16>(p, s, la);
@@ -675,6 +739,111 @@ hipError_t factor_run(const FactorPlan& p, hipStream_t s, Lookahead* la) {
     if (u == F16 && t == F32) return factor_typed<F32, F16>(p, s, la);
     if (u == BF16 && t == F32) return factor_typed<F32, BF16>(p, s, la);
     return hipErrorInvalidValue;
+}
+
+template <int ST, int OP>
+static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t s) {
+    typedef typename Operand<OP>::T OP_T;
+    hipError_t e;
+    if ((e = hipFuncSetAttribute((const void*)k_trsm<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)trsm_smem(1024))))
+        return e;
+    if ((e = hipFuncSetAttribute((const void*)k_inv_upper, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)trsm_smem(1024))))
+        return e;
+    if ((e = hipFuncSetAttribute((const void*)k_inv_lower, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)trsm_smem(1024))))
+        return e;
+    int64_t steps = 0;
+    for (int g = 0; g < count; ++g) {
+        const FactorPlan& p = P[g];
+        if ((e = fill_u64(p.info, 1, ~0ull, s))) return e;
+        const int64_t nblk = (p.n + p.nb - 1) / p.nb;
+        const int64_t words = nblk * (int64_t)diag_sync_words();
+        if ((e = fill_u64(p.dsync, (words + 1) / 2, 0ull, s))) return e;
+        steps = nblk > steps ? nblk : steps;
+    }
+    for (int64_t t = 0; t < steps; ++t) {
+        DiagCall dc[GEMM_GROUP_MAX];
+        TrsmGroup tg;
+        GemmCall gc[GEMM_GROUP_MAX];
+        int nd = 0, nt = 0, ng = 0, wg = 0, nbmax = 64;
+        for (int g = 0; g < count; ++g) {
+            const FactorPlan& p = P[g];
+            const int nb = (int)p.nb;
+            const int64_t k = t * nb;
+            if (k >= p.n) continue;
+            const int kb = (int)(p.n - k < nb ? p.n - k : nb);
+            const int64_t blk = k / nb, m = p.n - k - kb;
+            dc[nd++] = DiagCall{p.A, p.lda, k, kb, (int)rup(kb, 64), nb, p.T + blk * nb * nb, p.Trm + blk * nb * nb,
+                                p.linv + blk * nb * 64, p.uinv + blk * nb * 64, p.dsync + blk * diag_sync_words(),
+                                p.info};
+            if (m <= 0) continue;
+            trsm_desc<ST, OP>(p, k, tg.g[nt], wg);
+            wg = tg.g[nt++].wg_end;
+            nbmax = nb > nbmax ? nb : nbmax;
+            const int set = (int)(blk & 1);
+            const int64_t opset = p.op_rows * nb, scset = p.op_rows / 32;
+            gc[ng++] = GemmCall{(typename Store<ST>::T*)p.A + (k + nb) + (k + nb) * p.lda, p.lda, m, m, nb,
+                                (const OP_T*)p.Lq + set * opset, (const OP_T*)p.Uq + set * opset,
+                                p.inv_sa + set * scset, p.inv_sb + set * scset};
+        }
+        if ((e = diag_lu_group(ST, dc, nd, s))) return e;
+        if (nt) {
+            tg.count = nt;
+            hipEvent_t pt = prof::begin(prof::TRSM, s);
+            k_trsm<ST, OP><<<wg, 256, trsm_smem(nbmax), s>>>(tg);
+            prof::end(pt, prof::TRSM, s, 0.0, 0.0);
+            if ((e = hipGetLastError())) return e;
+            hipEvent_t pg = prof::begin(prof::GEMM, s);
+            if ((e = gemm_group(OP, ST, P[0].gemm_tile, gc, ng, s))) return e;
+            double fl = 0, by = 0;
+            for (int i = 0; i < ng; ++i) {
+                fl += 2.0 * gc[i].M * (double)gc[i].N * gc[i].K;
+                by += 2.0 * gc[i].M * (double)gc[i].N * sizeof(typename Store<ST>::T) +
+                      (gc[i].M + gc[i].N) * (double)gc[i].K * sizeof(OP_T);
+            }
+            prof::end(pg, prof::GEMM, s, fl, by);
+        }
+    }
+    for (int g = 0; g < count; ++g) {
+        const FactorPlan& p = P[g];
+        const int nb = (int)p.nb;
+        const int64_t nblk = (p.n + nb - 1) / nb;
+        dim3 gr((unsigned)(nb / SR), (unsigned)nblk);
+        k_inv_upper<<<gr, 256, trsm_smem(nb), s>>>(p.n, nb, p.Trm, p.uinv, p.uinv_full);
+        k_inv_lower<<<gr, 256, trsm_smem(nb), s>>>(p.n, nb, p.T, p.linv, p.linv_full);
+        if ((e = hipGetLastError())) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t factor_group(const FactorPlan* P, int count, hipStream_t s) {
+    if (count < 1 || count > GEMM_GROUP_MAX) return hipErrorInvalidValue;
+    for (int g = 1; g < count; ++g)
+        if (P[g].update != P[0].update || P[g].store != P[0].store) return hipErrorInvalidValue;
+    const int u = P[0].update, t = P[0].store;
+    if (u == F32 && t == F32) return factor_group_typed<F32, F32>(P, count, s);
+    if (u == F16 && t == F16) return factor_group_typed<F16, F16>(P, count, s);
+    if (u == BF16 && t == BF16) return factor_group_typed<BF16, BF16>(P, count, s);
+    if (u == F8 && t == F16) return factor_group_typed<F16, F8>(P, count, s);
+    if (u == F8 && t == BF16) return factor_group_typed<BF16, F8>(P, count, s);
+    if (u == F16 && t == F32) return factor_group_typed<F32, F16>(P, count, s);
+    if (u == BF16 && t == F32) return factor_group_typed<F32, BF16>(P, count, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t factor_run(const FactorPlan& p, hipStream_t s, Lookahead* la) {
+    if (la) return factor_dispatch(p, s, la);
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    Lookahead* L = nullptr;
+    if ((e = lookahead_acquire(dev, &L))) return e;
+    e = factor_dispatch(p, s, L);
+    lookahead_release(dev, L);
+    return e;
 }
 
 }  // namespace mxp

@@ -10,7 +10,7 @@
 namespace mxp {
 namespace prof {
 
-enum Cls : int { GEMM = 0, TRSM = 1, DIAG = 2, PREC = 3, REGEN = 4, GMRES = 5, NCLS = 6 };
+enum Cls : int { GEMM = 0, TRSM = 1, DIAG = 2, PREC = 3, REGEN = 4, GMRES = 5, GEMM64 = 6, NCLS = 7 };
 
 bool enabled();
 // begin() records a start event on s and returns it (nullptr when timing of

@@ -10,11 +10,17 @@
 //     as soon as a slot is idle and its bytes fit, so requests arriving while
 //     others run start as slots and memory free up (arrival order is kept,
 //     which bounds the wait of large requests);
-//   * slots: each is a host thread with its own stream and look-ahead
-//     context, so the kernels of requests in flight overlap on the device;
-//   * a block-size tuner: per size class (powers of two 512 .. 16384) the
-//     candidate block sizes are timed on the device at creation and the
-//     fastest is kept.
+//   * workers: a few host threads (at most three, fewer than the device's four
+//     hardware queues), each with one stream.  A worker takes a group of up
+//     to eight admitted requests and factors them together: per block step
+//     ONE launch of the diagonal-block LU, ONE of the strip TRSMs and ONE of
+//     the trailing update serve the whole group through descriptor arrays
+//     (mxp_factor_group).  It then refines each request with all of its
+//     right-hand sides in lockstep (mxp_solve_ir) and hands it back as soon
+//     as its own refinement ends.  The workers' groups overlap on the device;
+//   * a tuner: per size class (powers of two 512 .. 16384) it times every
+//     candidate pair of block size and trailing-update tile at creation and
+//     keeps the fastest.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -127,6 +133,9 @@ struct Req {
 
 constexpr int NCLASS = 6;           // size classes 512 << c
 const int64_t NB_CANDIDATES[] = {128, 256, 512};
+const int TILE_CANDIDATES[] = {MXP_TILE_256x128, MXP_TILE_128x128};
+constexpr int MAX_WORKERS = 3;
+constexpr int MAX_GROUP = 8;
 
 int size_class(int64_t n) {
     const int c = (int)std::lround(std::log2((double)std::max<int64_t>(n, 1))) - 9;
@@ -149,90 +158,102 @@ struct mxp_server {
     std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
     uint64_t next_id = 1;
     bool stop = false;
-    struct Slot {
+    struct Worker {
         std::thread th;
         hipStream_t s = nullptr;
-        Lookahead la;
     };
-    std::vector<Slot> slots;
-    int64_t submitted = 0, completed = 0, failed = 0, in_flight = 0, peak_in_flight = 0;
+    std::vector<Worker> workers;
+    int group_max = 1;
+    int64_t submitted = 0, completed = 0, failed = 0, in_flight = 0, peak_in_flight = 0, groups = 0,
+            grouped_requests = 0, peak_group = 0;
     size_t peak_bytes = 0;
     int64_t nb_class[NCLASS] = {128, 128, 256, 256, 512, 512};
+    int tile_class[NCLASS] = {MXP_TILE_128x128, MXP_TILE_128x128, MXP_TILE_128x128,
+                              MXP_TILE_256x128, MXP_TILE_256x128, MXP_TILE_256x128};
     std::chrono::steady_clock::time_point t0;
 
     int64_t now_ns() const {
         return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
     }
     int64_t block_size(int64_t n) const { return cfg.nb > 0 ? cfg.nb : nb_class[size_class(n)]; }
+    int tile(int64_t n) const { return tile_class[size_class(n)]; }
 };
 
 namespace {
 
-// generate + factor + refine one request in its arena block, on the slot's
-// stream; returns the first non-OK status
-int run_request(mxp_server* S, mxp_server::Slot& sl, Req* r) {
+struct ReqBufs {
+    ReqLayout L;
+    char* b;
+    void* A;
+    double *B, *X, *diag, *ainf;
+};
+
+ReqBufs bufs_of(mxp_server* S, Req* r) {
     const mxp_server_cfg& c = S->cfg;
-    const ReqLayout L = req_layout(r->n, r->nrhs, r->nb, c.update, c.store, c.restart);
-    char* b = S->base + r->off;
-    void* A = b + L.A;
-    double* B = (double*)(b + L.B);
-    double* X = (double*)(b + L.X);
-    double* diag = (double*)(b + L.diag);
-    double* ainf = (double*)(b + L.ainf);
-    int rc = mxp_generate(r->n, r->nrhs, r->seed, c.store, A, L.lda, B, r->n, diag, ainf, sl.s);
-    if (rc) return rc;
-    int64_t info = 0;
-    rc = factor_with(r->n, r->nb, c.update, c.store, MXP_SCALE_NONE, diag, A, L.lda, b + L.aux, b + L.fwork,
-                     L.fwork_bytes, &info, sl.s, &sl.la);
-    if (rc) return rc;
-    std::vector<mxp_rhs_report> rep((size_t)r->nrhs);
-    rc = mxp_solve_ir(r->n, r->nb, c.update, c.store, r->seed, A, L.lda, b + L.aux, diag, ainf, B, r->n, X, r->n,
-                      r->nrhs, c.restart, c.max_iters, c.tol, c.tau, rep.data(), b + L.swork, L.swork_bytes, sl.s);
-    for (const mxp_rhs_report& q : rep) {
-        r->iters = std::max<int64_t>(r->iters, q.iters);
-        r->eta = std::max(r->eta, q.eta);
-    }
-    if (rc < 0) return rc;
-    if (r->x_host) {
-        if (hipMemcpyAsync(r->x_host, X, (size_t)r->n * r->nrhs * 8, hipMemcpyDeviceToHost, sl.s) != hipSuccess ||
-            hipStreamSynchronize(sl.s) != hipSuccess)
-            return MXP_EHIP;
-    }
-    return rc;
+    ReqBufs q;
+    q.L = req_layout(r->n, r->nrhs, r->nb, c.update, c.store, c.restart);
+    q.b = S->base + r->off;
+    q.A = q.b + q.L.A;
+    q.B = (double*)(q.b + q.L.B);
+    q.X = (double*)(q.b + q.L.X);
+    q.diag = (double*)(q.b + q.L.diag);
+    q.ainf = (double*)(q.b + q.L.ainf);
+    return q;
 }
 
-void slot_main(mxp_server* S, int k) {
-    mxp_server::Slot& sl = S->slots[(size_t)k];
-    // a slot that cannot select the server's device fails every request it takes
-    const bool dev_ok = hipSetDevice(S->device) == hipSuccess;
-    for (;;) {
-        Req* r = nullptr;
-        {
-            std::unique_lock<std::mutex> lock(S->mu);
-            S->cv_work.wait(lock, [&] {
-                if (S->stop) return true;
-                size_t off;
-                if (S->queue.empty() || !S->arena.alloc(S->queue.front()->bytes, &off)) return false;
-                S->queue.front()->off = off;
-                return true;
-            });
-            if (S->stop) return;   // destroy drains first: nothing is queued any more
-            r = S->queue.front();
-            S->queue.pop_front();
-            r->t_start = S->now_ns();
-            S->in_flight++;
-            S->peak_in_flight = std::max(S->peak_in_flight, S->in_flight);
-            S->peak_bytes = std::max(S->peak_bytes, S->arena.used());
+// generate + factor (grouped) + refine a group of requests in their arena
+// blocks on the worker's stream; each request is completed as soon as its
+// own refinement is done
+void run_group(mxp_server* S, mxp_server::Worker& w, std::vector<Req*>& grp, bool dev_ok) {
+    const mxp_server_cfg& c = S->cfg;
+    const int G = (int)grp.size();
+    std::vector<ReqBufs> bq((size_t)G);
+    std::vector<int> rc((size_t)G, dev_ok ? MXP_OK : MXP_EHIP);
+    std::vector<mxp_factor_item> items;
+    std::vector<int> idx;
+    for (int g = 0; g < G && dev_ok; ++g) {
+        Req* r = grp[(size_t)g];
+        bq[(size_t)g] = bufs_of(S, r);
+        const ReqBufs& q = bq[(size_t)g];
+        rc[(size_t)g] = mxp_generate(r->n, r->nrhs, r->seed, MXP_GEN_DOMINANT, 0.0, c.store, q.A, q.L.lda, q.B, r->n,
+                                     q.diag, nullptr, q.ainf, w.s);
+        if (rc[(size_t)g]) continue;
+        items.push_back(mxp_factor_item{r->n, r->nb, q.A, q.L.lda, q.b + q.L.aux, q.b + q.L.fwork, q.L.fwork_bytes});
+        idx.push_back(g);
+    }
+    if (!items.empty()) {
+        std::vector<int64_t> info(items.size(), 0);
+        const int frc = mxp_factor_group((int)items.size(), items.data(), c.update, c.store, S->tile(grp[(size_t)idx[0]]->n),
+                                         info.data(), w.s);
+        for (size_t i = 0; i < idx.size(); ++i)
+            if (frc < 0 || info[i]) rc[(size_t)idx[i]] = frc < 0 ? frc : MXP_ESINGULAR;
+    }
+    for (int g = 0; g < G; ++g) {
+        Req* r = grp[(size_t)g];
+        if (rc[(size_t)g] == MXP_OK) {
+            const ReqBufs& q = bq[(size_t)g];
+            std::vector<mxp_rhs_report> rep((size_t)r->nrhs);
+            int s = mxp_solve_ir(r->n, r->nb, c.update, c.store, r->seed, MXP_GEN_DOMINANT, q.A, q.L.lda,
+                                 q.b + q.L.aux, q.diag, q.ainf, q.B, r->n, q.X, r->n, r->nrhs, c.restart, c.max_iters,
+                                 c.tol, c.tau, rep.data(), q.b + q.L.swork, q.L.swork_bytes, w.s);
+            for (const mxp_rhs_report& x : rep) {
+                r->iters = std::max<int64_t>(r->iters, x.iters);
+                r->eta = std::max(r->eta, x.eta);
+            }
+            if (s >= 0 && r->x_host &&
+                (hipMemcpyAsync(r->x_host, q.X, (size_t)r->n * r->nrhs * 8, hipMemcpyDeviceToHost, w.s) != hipSuccess ||
+                 hipStreamSynchronize(w.s) != hipSuccess))
+                s = MXP_EHIP;
+            rc[(size_t)g] = s;
         }
-        const int rc = dev_ok ? run_request(S, sl, r) : MXP_EHIP;
         {
             std::lock_guard<std::mutex> lock(S->mu);
             S->arena.release(r->off, r->bytes);
-            r->status = rc;
+            r->status = rc[(size_t)g];
             r->t_done = S->now_ns();
             r->done = true;
             S->in_flight--;
-            if (rc == MXP_OK) S->completed++;
+            if (r->status == MXP_OK) S->completed++;
             else S->failed++;
         }
         S->cv_work.notify_all();
@@ -240,9 +261,45 @@ void slot_main(mxp_server* S, int k) {
     }
 }
 
-// time factor + refinement of one size class for every candidate block size
+void worker_main(mxp_server* S, int k) {
+    mxp_server::Worker& w = S->workers[(size_t)k];
+    // a worker that cannot select the server's device fails every request it takes
+    const bool dev_ok = hipSetDevice(S->device) == hipSuccess;
+    for (;;) {
+        std::vector<Req*> grp;
+        {
+            std::unique_lock<std::mutex> lock(S->mu);
+            // the queue's head requests, in arrival order, while a slot is
+            // free and their bytes fit in the arena
+            S->cv_work.wait(lock, [&] {
+                if (S->stop) return true;
+                while (!S->queue.empty() && (int)grp.size() < S->group_max && S->in_flight < S->cfg.max_slots) {
+                    size_t off;
+                    Req* r = S->queue.front();
+                    if (!S->arena.alloc(r->bytes, &off)) break;
+                    r->off = off;
+                    r->t_start = S->now_ns();
+                    S->queue.pop_front();
+                    S->in_flight++;
+                    grp.push_back(r);
+                }
+                return !grp.empty();
+            });
+            if (S->stop && grp.empty()) return;   // destroy drains first: nothing is queued any more
+            S->peak_in_flight = std::max(S->peak_in_flight, S->in_flight);
+            S->peak_bytes = std::max(S->peak_bytes, S->arena.used());
+            S->groups++;
+            S->grouped_requests += (int64_t)grp.size();
+            S->peak_group = std::max<int64_t>(S->peak_group, (int64_t)grp.size());
+        }
+        run_group(S, w, grp, dev_ok);
+    }
+}
+
+// time factor + refinement of one size class for every candidate pair of
+// block size and trailing-update tile
 void autotune(mxp_server* S) {
-    mxp_server::Slot& sl = S->slots[0];
+    mxp_server::Worker& w = S->workers[0];
     const mxp_server_cfg& c = S->cfg;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return;
@@ -254,38 +311,43 @@ void autotune(mxp_server* S) {
         const int64_t n = 512ll << cls;
         float best = 0;
         for (int64_t nb : NB_CANDIDATES) {
+            if (c.update == MXP_F8E4M3 && nb % 128) continue;
             const ReqLayout L = req_layout(n, 1, nb, c.update, c.store, c.restart);
             if (L.total > S->arena.size()) continue;
-            Req r;
-            r.n = n; r.nrhs = 1; r.nb = nb; r.seed = 12345; r.off = 0;
-            float ms_min = 0;
-            bool ok = true;
-            for (int rep = 0; rep < 3 && ok; ++rep) {
-                // regenerated each time (the factorisation overwrites A); generation is not timed
-                char* b = S->base;
-                if (mxp_generate(n, 1, r.seed, c.store, b + L.A, L.lda, (double*)(b + L.B), n, (double*)(b + L.diag),
-                                 (double*)(b + L.ainf), sl.s)) { ok = false; break; }
-                if (hipEventRecord(e0, sl.s) != hipSuccess) { ok = false; break; }
-                int64_t info = 0;
-                std::vector<mxp_rhs_report> q(1);
-                int rc = factor_with(n, nb, c.update, c.store, MXP_SCALE_NONE, (double*)(b + L.diag), b + L.A, L.lda,
-                                     b + L.aux, b + L.fwork, L.fwork_bytes, &info, sl.s, &sl.la);
-                if (!rc)
-                    rc = mxp_solve_ir(n, nb, c.update, c.store, r.seed, b + L.A, L.lda, b + L.aux,
-                                      (double*)(b + L.diag), (double*)(b + L.ainf), (double*)(b + L.B), n,
-                                      (double*)(b + L.X), n, 1, c.restart, c.max_iters, c.tol, c.tau, q.data(),
-                                      b + L.swork, L.swork_bytes, sl.s);
-                if (rc != MXP_OK || hipEventRecord(e1, sl.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                    ok = false;
-                    break;
+            for (int tile : TILE_CANDIDATES) {
+                float ms_min = 0;
+                bool ok = true;
+                for (int rep = 0; rep < 3 && ok; ++rep) {
+                    // regenerated each time (the factorisation overwrites A); generation is not timed
+                    char* b = S->base;
+                    if (mxp_generate(n, 1, 12345, MXP_GEN_DOMINANT, 0.0, c.store, b + L.A, L.lda, (double*)(b + L.B),
+                                     n, (double*)(b + L.diag), nullptr, (double*)(b + L.ainf), w.s)) {
+                        ok = false;
+                        break;
+                    }
+                    if (hipEventRecord(e0, w.s) != hipSuccess) { ok = false; break; }
+                    int64_t info = 0;
+                    mxp_factor_item it{n, nb, b + L.A, L.lda, b + L.aux, b + L.fwork, L.fwork_bytes};
+                    std::vector<mxp_rhs_report> q(1);
+                    int rc = mxp_factor_group(1, &it, c.update, c.store, tile, &info, w.s);
+                    if (!rc)
+                        rc = mxp_solve_ir(n, nb, c.update, c.store, 12345, MXP_GEN_DOMINANT, b + L.A, L.lda, b + L.aux,
+                                          (double*)(b + L.diag), (double*)(b + L.ainf), (double*)(b + L.B), n,
+                                          (double*)(b + L.X), n, 1, c.restart, c.max_iters, c.tol, c.tau, q.data(),
+                                          b + L.swork, L.swork_bytes, w.s);
+                    if (rc != MXP_OK || hipEventRecord(e1, w.s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        ok = false;
+                        break;
+                    }
+                    float ms = 0;
+                    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { ok = false; break; }
+                    if (rep > 0 && (ms_min == 0 || ms < ms_min)) ms_min = ms;   // the first run warms up
                 }
-                float ms = 0;
-                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { ok = false; break; }
-                if (rep > 0 && (ms_min == 0 || ms < ms_min)) ms_min = ms;   // the first run warms up
-            }
-            if (ok && (best == 0 || ms_min < best)) {
-                best = ms_min;
-                S->nb_class[cls] = nb;
+                if (ok && (best == 0 || ms_min < best)) {
+                    best = ms_min;
+                    S->nb_class[cls] = nb;
+                    S->tile_class[cls] = tile;
+                }
             }
         }
     }
@@ -314,24 +376,25 @@ extern "C" int mxp_server_create(int device, void* arena, size_t arena_bytes, co
     S->cfg = *cfg;
     S->arena.init(arena_bytes);
     S->t0 = std::chrono::steady_clock::now();
-    S->slots.resize((size_t)cfg->max_slots);
+    // a few workers with one stream each, groups that share the slots
+    const int nw = std::min(cfg->max_slots, MAX_WORKERS);
+    S->group_max = std::min(MAX_GROUP, (cfg->max_slots + nw - 1) / nw);
+    S->workers.resize((size_t)nw);
     int rc = MXP_OK;
-    for (auto& sl : S->slots) {
-        if (hipStreamCreateWithFlags(&sl.s, hipStreamNonBlocking) != hipSuccess || lookahead_create(&sl.la)) {
+    for (auto& w : S->workers) {
+        if (hipStreamCreateWithFlags(&w.s, hipStreamNonBlocking) != hipSuccess) {
             rc = MXP_EHIP;
             break;
         }
     }
     if (rc == MXP_OK && cfg->autotune && cfg->nb == 0) autotune(S.get());
     if (rc != MXP_OK) {
-        for (auto& sl : S->slots) {
-            lookahead_destroy(&sl.la);
-            if (sl.s) (void)hipStreamDestroy(sl.s);
-        }
+        for (auto& w : S->workers)
+            if (w.s) (void)hipStreamDestroy(w.s);
         (void)hipSetDevice(prev);   // restores the caller's device
         return rc;
     }
-    for (int k = 0; k < cfg->max_slots; ++k) S->slots[(size_t)k].th = std::thread(slot_main, S.get(), k);
+    for (int k = 0; k < nw; ++k) S->workers[(size_t)k].th = std::thread(worker_main, S.get(), k);
     (void)hipSetDevice(prev);
     *out = S.release();
     return MXP_OK;
@@ -414,10 +477,16 @@ extern "C" int mxp_server_get_stats(mxp_server* S, mxp_server_stats* out) {
     out->arena_bytes = S->arena.size();
     out->bytes_in_use = S->arena.used();
     out->peak_bytes_in_use = S->peak_bytes;
+    out->groups = S->groups;
+    out->grouped_requests = S->grouped_requests;
+    out->peak_group = S->peak_group;
+    out->streams = (int64_t)S->workers.size();
     return MXP_OK;
 }
 
 extern "C" int64_t mxp_server_block_size(mxp_server* S, int64_t n) { return S ? S->block_size(n) : 0; }
+
+extern "C" int mxp_server_tile(mxp_server* S, int64_t n) { return S ? S->tile(n) : -1; }
 
 extern "C" int mxp_server_destroy(mxp_server* S) {
     if (!S) return MXP_EINVAL;
@@ -427,17 +496,15 @@ extern "C" int mxp_server_destroy(mxp_server* S) {
         S->stop = true;
     }
     S->cv_work.notify_all();
-    for (auto& sl : S->slots)
-        if (sl.th.joinable()) sl.th.join();
-    // teardown: the streams and events are released on the server's device,
-    // whatever those calls return
+    for (auto& w : S->workers)
+        if (w.th.joinable()) w.th.join();
+    // teardown: the streams are released on the server's device, whatever
+    // those calls return
     int prev = 0;
     (void)hipGetDevice(&prev);
     (void)hipSetDevice(S->device);
-    for (auto& sl : S->slots) {
-        lookahead_destroy(&sl.la);
-        if (sl.s) (void)hipStreamDestroy(sl.s);
-    }
+    for (auto& w : S->workers)
+        if (w.s) (void)hipStreamDestroy(w.s);
     (void)hipSetDevice(prev);
     delete S;
     return MXP_OK;

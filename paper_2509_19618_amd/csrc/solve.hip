@@ -26,8 +26,9 @@ __global__ __launch_bounds__(256) void k_scale_rows(int64_t n, const double* __r
 }
 
 // ---------------------------------------------------------------- block substitution
-// One kernel per triangular solve.  Work-group = one strip of TS rows; strips
-// are processed as a dataflow: a strip of block j accumulates the products of
+// One kernel per triangular solve, every right-hand side at once (one row of
+// work-groups per right-hand side, each with its own flags).  Work-group = one
+// strip of TS rows; strips are processed as a dataflow: a strip of block j accumulates the products of
 // its rows of the off-diagonal factor with every dependency block's solution
 // as soon as that block is published (flag `ready`), then the strips of block
 // j meet (flag `cnt`) and each applies its rows of the FP32 inverse of the
@@ -42,9 +43,10 @@ constexpr int TS = 64;
 
 // Values exchanged between work-groups (block solutions, block right-hand
 // sides) are written and read with device-scope atomic accesses, which go to
-// the device's coherence point instead of an XCD's L2; a flag is raised only
-// after every wave has its stores acknowledged, so no cache write-back or
-// invalidation is needed.
+// the device's coherence point instead of an XCD's L2.  A flag is raised
+// after every wave's stores are released (sync_release) and a work-group
+// barrier; a waiter that sees the flag reads after it (sync_acquire, then
+// the barrier that lets its other threads read); see common.hpp.
 MXP_DEV void put_shared(double* p, double v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 MXP_DEV double get_shared(const double* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
@@ -85,26 +87,31 @@ __device__ bool wait_flag(const unsigned* flag, unsigned target, int* err, int* 
             }
             __builtin_amdgcn_s_sleep(2);
         }
+        if (ok) sync_acquire();
         *s_abort = !ok;
     }
     __syncthreads();
     return !*s_abort;
 }
 
-// every wave waits for its stores to be acknowledged, then the flag counts
-// one more strip
+// every wave's stores are released at agent scope and precede the barrier;
+// the flag then counts one more strip with release semantics
 __device__ void signal_flag(unsigned* flag) {
-    __builtin_amdgcn_s_waitcnt(0);
+    sync_release();
     __syncthreads();
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+        sync_release();
+        __hip_atomic_fetch_add(flag, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
 }
 
 template <int ST, bool LOWER>
 __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename Store<ST>::T* __restrict__ A,
                                               int64_t lda, int vec, const float* __restrict__ inv_all,
                                               const float* __restrict__ lsc, int64_t nstrips32,
-                                              const double* __restrict__ rhs, double* __restrict__ tbuf,
-                                              double* __restrict__ out, unsigned* flags, int* err) {
+                                              const double* __restrict__ rhs, int64_t ld_rhs,
+                                              double* __restrict__ tbuf, double* __restrict__ out, int64_t ld_out,
+                                              unsigned* flags, int64_t flag_stride, int* err) {
     typedef typename Store<ST>::T T;
     constexpr int RPL = 16 / (int)sizeof(T);   // rows per lane: one 16-byte load
     constexpr int RG = TS / RPL;               // lanes per column
@@ -115,6 +122,11 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
     __shared__ double w[TS];
     __shared__ int s_abort;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    // right-hand side blockIdx.y: its own vectors, block buffer and flags
+    rhs += blockIdx.y * ld_rhs;
+    out += blockIdx.y * ld_out;
+    tbuf += blockIdx.y * n;
+    flags += blockIdx.y * flag_stride;
     const int64_t S = (n + TS - 1) / TS, J = (n + nb - 1) / nb;
     const int64_t sidx = LOWER ? (int64_t)blockIdx.x : S - 1 - (int64_t)blockIdx.x;
     const int64_t j = sidx / (nb / TS);
@@ -268,15 +280,17 @@ __global__ void k_zero_u32(unsigned* p, int64_t count) {
     if (i < count) p[i] = 0u;
 }
 
-static int64_t trsv_flag_words(int64_t n) { return 4 * (n / TS + 2) + 2; }
+// flag words of one right-hand side: cnt and ready of both solves (at most
+// ceil(n / 64) blocks each)
+static int64_t trsv_flag_words(int64_t n) { return 4 * (n / 64 + 2); }
 
 size_t prec_work_bytes(int64_t n, int nr) {
-    // R (n x nr), Y, Tb (n each), flags + error word
-    return (size_t)(n * nr + 2 * n) * 8 + (size_t)trsv_flag_words(n) * 4 + 256;
+    // S V, forward solution, block right-hand sides (n x nr each), flags, error word
+    return (size_t)(3 * n * nr) * 8 + (size_t)(trsv_flag_words(n) * nr) * 4 + 256;
 }
 
 static int* prec_err_word(double* W, int64_t n, int nr) {
-    return (int*)((unsigned*)(W + n * nr + 2 * n) + trsv_flag_words(n) - 2);
+    return (int*)((unsigned*)(W + 3 * n * nr) + trsv_flag_words(n) * nr);
 }
 
 hipError_t prec_err_reset(double* W, int64_t n, int nr, hipStream_t s) {
@@ -298,21 +312,22 @@ static hipError_t prec_typed(const PrecPlan& p, const double* V, int64_t ldv, do
     const int64_t J = (n + nb - 1) / nb;
     const int64_t nstrips32 = (n + 31) / 32;
     const int64_t S = (n + TS - 1) / TS;
-    double* R = W;                 // S V, nr columns
-    double* Y = W + n * nr;        // forward solution
-    double* Tb = Y + n;            // block right-hand sides
-    unsigned* flags = (unsigned*)(Tb + n);
+    double* R = W;                 // S V, nr columns (ld n)
+    double* Y = W + n * nr;        // forward solutions
+    double* Tb = Y + n * nr;       // block right-hand sides
+    unsigned* flags = (unsigned*)(Tb + n * nr);
+    const int64_t fw = trsv_flag_words(n);
     int* err = prec_err_word(W, n, nr);
     const int vec = ((p.lda * (int64_t)sizeof(T)) % 16 == 0 && ((uintptr_t)p.A) % 16 == 0) ? 1 : 0;
     hipEvent_t pt = prof::begin(prof::PREC, s);
     k_scale_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, p.rowscale, V, ldv, R, nr);
-    for (int r = 0; r < nr; ++r) {
-        k_zero_u32<<<(unsigned)((4 * J + 255) / 256), 256, 0, s>>>(flags, 4 * J);
-        k_trsv<ST, true><<<(unsigned)S, 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, vec, p.linv_full, p.lsc,
-                                                     nstrips32, R + r * n, Tb, Y, flags, err);
-        k_trsv<ST, false><<<(unsigned)S, 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, vec, p.uinv_full, nullptr,
-                                                      nstrips32, Y, Tb, Z + r * ldz, flags + 2 * J, err);
-    }
+    k_zero_u32<<<(unsigned)((fw * nr + 255) / 256), 256, 0, s>>>(flags, fw * nr);
+    k_trsv<ST, true><<<dim3((unsigned)S, (unsigned)nr), 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, vec,
+                                                                     p.linv_full, p.lsc, nstrips32, R, n, Tb, Y, n,
+                                                                     flags, fw, err);
+    k_trsv<ST, false><<<dim3((unsigned)S, (unsigned)nr), 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, vec,
+                                                                      p.uinv_full, nullptr, nstrips32, Y, n, Tb, Z,
+                                                                      ldz, flags + 2 * J, fw, err);
     prof::end(pt, prof::PREC, s, 2.0 * n * (double)n * nr, (double)n * n * sizeof(T) + 8.0 * n * nb);
     return hipGetLastError();
 }
@@ -327,10 +342,13 @@ hipError_t prec_apply(const PrecPlan& p, const double* V, int64_t ldv, double* Z
     }
 }
 
-// ================================================================ reductions
-// Every reduction kernel gives block b the fixed index range
-// [b*chunk, (b+1)*chunk) and sums it in a fixed order, so results are
-// identical from run to run.
+// ================================================================ GMRES vector kernels
+// Every right-hand side runs its own GMRES in lockstep with the others:
+// blockIdx.y (or the thread index of the scalar kernels) is the right-hand
+// side r, and act[r] says whether r takes part in the current step (the
+// others' blocks return at once).  Every reduction gives block b the fixed
+// index range [b*chunk, (b+1)*chunk) and sums it in a fixed order, so
+// results are identical from run to run.
 int red_blocks(int64_t n) {
     int64_t b = (n + 4095) / 4096;
     if (b > 256) b = 256;
@@ -353,157 +371,194 @@ __device__ __forceinline__ double sum_parts(const double* part, int nparts, doub
     return block_sum(v, red);
 }
 
-// partial dot of x and y over the block's range
-__global__ __launch_bounds__(256) void k_dot_part(int64_t n, int64_t chunk, const double* __restrict__ x,
-                                                  const double* __restrict__ y, double* __restrict__ part) {
+// part[r][b] = sum over block b's range of x_r . y_r
+__global__ __launch_bounds__(256) void k_dot_part(int64_t n, int64_t chunk, const double* __restrict__ x, int64_t ldx,
+                                                  const double* __restrict__ y, int64_t ldy, double* __restrict__ part,
+                                                  const int* __restrict__ act) {
     __shared__ double red[4];
-    int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
+    const int r = blockIdx.y;
+    if (!act[r]) return;
+    x += r * ldx;
+    y += r * ldy;
+    const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
     double v = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) v += x[i] * y[i];
     v = block_sum(v, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = v;
+    if (threadIdx.x == 0) part[r * 256 + blockIdx.x] = v;
 }
 
-// MGS step j: h_j = sum(part_in); w -= h_j v_j over the block's range; then the
-// partial dot for the next vector (v_{j+1} . w, or w . w after the last one).
-__global__ __launch_bounds__(256) void k_mgs(int64_t n, int64_t chunk, const double* __restrict__ vj,
-                                             const double* __restrict__ vnext, double* __restrict__ w,
-                                             const double* __restrict__ part_in, double* __restrict__ part_out,
-                                             double* __restrict__ hj) {
+// MGS step j of column k: h_jk = sum(part_in); w -= h_jk v_j over the
+// block's range; then the partial dot for the next vector (v_{j+1} . w, or
+// w . w after the last one).  V: basis vectors v_{r,j} at V + (j nr + r) n.
+__global__ __launch_bounds__(256) void k_mgs(int64_t n, int64_t chunk, int nr, const double* __restrict__ V, int j,
+                                             int last, double* __restrict__ W, const double* __restrict__ part_in,
+                                             double* __restrict__ part_out, double* __restrict__ H, int ldh, int k,
+                                             const int* __restrict__ act) {
     __shared__ double red[4];
-    double h = sum_parts(part_in, gridDim.x, red);
-    if (blockIdx.x == 0 && threadIdx.x == 0) *hj = h;
-    int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
+    const int r = blockIdx.y;
+    if (!act[r]) return;
+    const double* vj = V + ((int64_t)j * nr + r) * n;
+    const double* vnext = last ? nullptr : V + ((int64_t)(j + 1) * nr + r) * n;
+    double* w = W + (int64_t)r * n;
+    const double h = sum_parts(part_in + r * 256, gridDim.x, red);
+    if (blockIdx.x == 0 && threadIdx.x == 0) H[(int64_t)r * ldh * (ldh - 1) + j + (int64_t)k * ldh] = h;
+    const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
     double v = 0.0;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-        double wi = w[i] - h * vj[i];
+        const double wi = w[i] - h * vj[i];
         w[i] = wi;
         v += (vnext ? vnext[i] : wi) * wi;
     }
     v = block_sum(v, red);
-    if (threadIdx.x == 0) part_out[blockIdx.x] = v;
+    if (threadIdx.x == 0) part_out[r * 256 + blockIdx.x] = v;
 }
 
-hipError_t mgs_step(int64_t n, const double* V, int k, double* w, double* hcol, double* part, hipStream_t s) {
-    // V: n x (k+1) basis vectors v_0..v_k (column stride n); part: 2 x 256 scratch
-    int nbk = red_blocks(n);
-    int64_t chunk = (n + nbk - 1) / nbk;
-    k_dot_part<<<nbk, 256, 0, s>>>(n, chunk, V, w, part);
-    for (int j = 0; j <= k; ++j) {
-        const double* vnext = (j < k) ? V + (int64_t)(j + 1) * n : nullptr;
-        double* pin = part + (j & 1) * 256;
-        double* pout = part + ((j + 1) & 1) * 256;
-        k_mgs<<<nbk, 256, 0, s>>>(n, chunk, V + (int64_t)j * n, vnext, w, pin, pout, hcol + j);
-    }
-    return hipGetLastError();
-}
-
-// h = sqrt(sum(part)) ; v = w / h (v = 0 on exact breakdown)
-__global__ __launch_bounds__(256) void k_normalize(int64_t n, int64_t chunk, const double* __restrict__ part,
-                                                   const double* __restrict__ w, double* __restrict__ v,
-                                                   double* __restrict__ hsub) {
+// h = sqrt(sum(part)); H[k+1][k] = h; v_{k+1} = w / h (0 on exact breakdown)
+__global__ __launch_bounds__(256) void k_normalize(int64_t n, int64_t chunk, int nr, const double* __restrict__ part,
+                                                   const double* __restrict__ W, double* __restrict__ V, int k,
+                                                   double* __restrict__ H, int ldh, const int* __restrict__ act) {
     __shared__ double red[4];
-    double h = sqrt(sum_parts(part, gridDim.x, red));
-    if (blockIdx.x == 0 && threadIdx.x == 0) *hsub = h;
-    int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
+    const int r = blockIdx.y;
+    if (!act[r]) return;
+    const double h = sqrt(sum_parts(part + r * 256, gridDim.x, red));
+    if (blockIdx.x == 0 && threadIdx.x == 0) H[(int64_t)r * ldh * (ldh - 1) + (k + 1) + (int64_t)k * ldh] = h;
+    const double* w = W + (int64_t)r * n;
+    double* v = V + ((int64_t)(k + 1) * nr + r) * n;
+    const int64_t i0 = (int64_t)blockIdx.x * chunk, i1 = i0 + chunk < n ? i0 + chunk : n;
     for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) v[i] = (h > 0.0) ? w[i] / h : 0.0;
 }
 
-hipError_t norm_normalize(int64_t n, double* w, double* vout, double* hsub, double* part, hipStream_t s) {
-    int nbk = red_blocks(n);
-    int64_t chunk = (n + nbk - 1) / nbk;
-    k_normalize<<<nbk, 256, 0, s>>>(n, chunk, part, w, vout, hsub);
-    return hipGetLastError();
-}
-
-__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ part, int nparts, double* out) {
+// out[r] = sqrt(sum(part[r]))
+__global__ __launch_bounds__(256) void k_norm_final(const double* __restrict__ part, int nparts, double* out,
+                                                    int out_stride, const int* __restrict__ act) {
     __shared__ double red[4];
-    double v = sum_parts(part, nparts, red);
-    if (threadIdx.x == 0) *out = sqrt(v);
+    const int r = blockIdx.x;
+    if (!act[r]) return;
+    const double v = sum_parts(part + r * 256, nparts, red);
+    if (threadIdx.x == 0) out[r * out_stride] = sqrt(v);
 }
 
-hipError_t vec_norm2(int64_t n, const double* x, double* out, double* part, hipStream_t s) {
-    int nbk = red_blocks(n);
-    int64_t chunk = (n + nbk - 1) / nbk;
-    k_dot_part<<<nbk, 256, 0, s>>>(n, chunk, x, x, part);
-    k_norm_final<<<1, 256, 0, s>>>(part, nbk, out);
-    return hipGetLastError();
+// v_{r,0} = z_r / beta_r; g_r = beta_r e_1
+__global__ __launch_bounds__(256) void k_start_basis(int64_t n, const double* __restrict__ Z, const double* sc,
+                                                     int sc_stride, double* __restrict__ V, int nr,
+                                                     double* __restrict__ g, int ldg, const int* __restrict__ act) {
+    const int r = blockIdx.y;
+    if (!act[r]) return;
+    const double b = sc[r * sc_stride];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (blockIdx.x == 0 && threadIdx.x < ldg) g[r * ldg + threadIdx.x] = threadIdx.x == 0 ? b : 0.0;
+    if (i < n) V[(int64_t)r * n + i] = (b > 0.0) ? Z[(int64_t)r * n + i] / b : 0.0;
 }
 
-// v = z / beta ; g[0] = beta
-__global__ __launch_bounds__(256) void k_scale_copy(int64_t n, const double* __restrict__ z,
-                                                    const double* __restrict__ beta, double* __restrict__ v,
-                                                    double* __restrict__ g0) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    double b = beta[0];
-    if (i == 0) g0[0] = b;
-    if (i < n) v[i] = (b > 0.0) ? z[i] / b : 0.0;
-}
-
-hipError_t vec_scale_copy(int64_t n, const double* x, const double* beta, double* v, double* g0, hipStream_t s) {
-    k_scale_copy<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, x, beta, v, g0);
-    return hipGetLastError();
-}
-
-// ================================================================ Givens / least squares
-// Column k of H (column-major, ldh): apply rotations 0..k-1, form rotation k
-// that zeroes H[k+1,k], rotate g.  flag[0] = |g[k+1]|, flag[1] = 1 when
-// |g[k+1]| <= tau * xnorm or H[k+1,k] was 0 (exact breakdown).
-__global__ void k_givens(int k, double* H, int ldh, double* cs, double* sn, double* g, const double* xnorm,
-                         double tau, double* flag) {
-    if (threadIdx.x != 0) return;
-    double* h = H + (int64_t)k * ldh;
-    double hsub = h[k + 1];
+// Column k of each active H_r (column-major, ldh = m + 1): apply rotations
+// 0..k-1, form rotation k that zeroes H[k+1][k], rotate g.  flag[r] = 1 when
+// |g[k+1]| <= tau ||x_r|| or H[k+1][k] was 0 (exact breakdown).
+__global__ void k_givens(int nr, int k, double* H, int ldh, double* cs, double* sn, double* g,
+                         const double* sc, int sc_stride, double tau, int* flag, const int* __restrict__ act) {
+    const int r = threadIdx.x;
+    if (r >= nr || !act[r]) return;
+    double* h = H + (int64_t)r * ldh * (ldh - 1) + (int64_t)k * ldh;
+    double* c_ = cs + r * ldh;
+    double* s_ = sn + r * ldh;
+    double* gr = g + r * ldh;
+    const double hsub = h[k + 1];
     for (int i = 0; i < k; ++i) {
-        double a = h[i], b = h[i + 1];
-        h[i] = cs[i] * a + sn[i] * b;
-        h[i + 1] = -sn[i] * a + cs[i] * b;
+        const double a = h[i], b = h[i + 1];
+        h[i] = c_[i] * a + s_[i] * b;
+        h[i + 1] = -s_[i] * a + c_[i] * b;
     }
-    double a = h[k], b = h[k + 1];
-    double rho = hypot(a, b);
-    double c = (rho > 0.0) ? a / rho : 1.0, s = (rho > 0.0) ? b / rho : 0.0;
-    cs[k] = c;
-    sn[k] = s;
+    const double a = h[k], b = h[k + 1];
+    const double rho = hypot(a, b);
+    const double c = (rho > 0.0) ? a / rho : 1.0, s = (rho > 0.0) ? b / rho : 0.0;
+    c_[k] = c;
+    s_[k] = s;
     h[k] = rho;
     h[k + 1] = 0.0;
-    double gk = g[k];
-    g[k + 1] = -s * gk;
-    g[k] = c * gk;
-    flag[0] = fabs(g[k + 1]);
-    flag[1] = (fabs(g[k + 1]) <= tau * xnorm[0] || hsub == 0.0) ? 1.0 : 0.0;
+    const double gk = gr[k];
+    gr[k + 1] = -s * gk;
+    gr[k] = c * gk;
+    const double xnorm = sc[r * sc_stride];
+    flag[r] = (fabs(gr[k + 1]) <= tau * xnorm || hsub == 0.0) ? 1 : 0;
 }
 
-hipError_t givens_step(int k, double* H, int ldh, double* cs, double* sn, double* g, const double* xnorm, double tau,
-                       double* flag, hipStream_t s) {
-    k_givens<<<1, 64, 0, s>>>(k, H, ldh, cs, sn, g, xnorm, tau, flag);
-    return hipGetLastError();
-}
-
-// y = R^-1 g (R = rotated H[0:k, 0:k], upper triangular)
-__global__ void k_backsub(int k, const double* H, int ldh, const double* g, double* y) {
-    if (threadIdx.x != 0) return;
+// y_r = R_r^-1 g_r (R_r = rotated H_r[0:k_r, 0:k_r]), k_r = kdim[r]
+__global__ void k_backsub(int nr, const double* H, int ldh, const double* g, double* y, const int* kdim) {
+    const int r = threadIdx.x;
+    if (r >= nr) return;
+    const int k = kdim[r];
+    const double* Hr = H + (int64_t)r * ldh * (ldh - 1);
+    const double* gr = g + r * ldh;
+    double* yr = y + r * ldh;
     for (int i = k - 1; i >= 0; --i) {
-        double t = g[i];
-        for (int l = i + 1; l < k; ++l) t -= H[i + (int64_t)l * ldh] * y[l];
-        y[i] = t / H[i + (int64_t)i * ldh];
+        double t = gr[i];
+        for (int l = i + 1; l < k; ++l) t -= Hr[i + (int64_t)l * ldh] * yr[l];
+        yr[i] = t / Hr[i + (int64_t)i * ldh];
     }
 }
 
-// x += V[:, 0:k] y
-__global__ __launch_bounds__(256) void k_axpy_basis(int64_t n, int k, const double* __restrict__ V,
-                                                    const double* __restrict__ y, double* __restrict__ x) {
-    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
+// x_r += V_r[:, 0:k_r] y_r
+__global__ __launch_bounds__(256) void k_axpy_basis(int64_t n, int nr, const double* __restrict__ V,
+                                                    const double* __restrict__ y, int ldy, const int* kdim,
+                                                    double* __restrict__ X, int64_t ldx) {
+    const int r = blockIdx.y;
+    const int k = kdim[r];
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n || k == 0) return;
     double acc = 0.0;
-    for (int j = 0; j < k; ++j) acc += y[j] * V[i + (int64_t)j * n];
-    x[i] += acc;
+    for (int j = 0; j < k; ++j) acc += y[r * ldy + j] * V[((int64_t)j * nr + r) * n + i];
+    X[r * ldx + i] += acc;
 }
 
-hipError_t lsq_update(int64_t n, int k, const double* H, int ldh, const double* g, double* y, const double* V,
-                      double* x, hipStream_t s) {
-    if (k <= 0) return hipSuccess;
-    k_backsub<<<1, 64, 0, s>>>(k, H, ldh, g, y);
-    k_axpy_basis<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, k, V, y, x);
+__global__ void k_set_i32(int* p, int n, const int* src) {
+    const int i = threadIdx.x;
+    if (i < n) p[i] = src ? src[i] : 0;
+}
+
+// ---- host wrappers (all right-hand sides at once; V is (m + 1) x nr x n)
+hipError_t gm_norms(int64_t n, int nr, const double* X, int64_t ldx, double* out, int out_stride, double* part,
+                    const int* act, hipStream_t s) {
+    const int nbk = red_blocks(n);
+    const int64_t chunk = (n + nbk - 1) / nbk;
+    k_dot_part<<<dim3(nbk, nr), 256, 0, s>>>(n, chunk, X, ldx, X, ldx, part, act);
+    k_norm_final<<<nr, 256, 0, s>>>(part, nbk, out, out_stride, act);
+    return hipGetLastError();
+}
+
+hipError_t gm_start(int64_t n, int nr, const double* Z, const double* sc, int sc_stride, double* V, double* g,
+                    int ldg, const int* act, hipStream_t s) {
+    k_start_basis<<<dim3((unsigned)((n + 255) / 256), nr), 256, 0, s>>>(n, Z, sc, sc_stride, V, nr, g, ldg, act);
+    return hipGetLastError();
+}
+
+hipError_t gm_arnoldi(int64_t n, int nr, double* V, int k, double* W, double* part, double* H, int ldh,
+                      const int* act, hipStream_t s) {
+    const int nbk = red_blocks(n);
+    const int64_t chunk = (n + nbk - 1) / nbk;
+    k_dot_part<<<dim3(nbk, nr), 256, 0, s>>>(n, chunk, V, n, W, n, part, act);
+    for (int j = 0; j <= k; ++j) {
+        const double* pin = part + (j & 1) * 256 * nr;
+        double* pout = part + ((j + 1) & 1) * 256 * nr;
+        k_mgs<<<dim3(nbk, nr), 256, 0, s>>>(n, chunk, nr, V, j, j == k, W, pin, pout, H, ldh, k, act);
+    }
+    k_normalize<<<dim3(nbk, nr), 256, 0, s>>>(n, chunk, nr, part + ((k + 1) & 1) * 256 * nr, W, V, k, H, ldh, act);
+    return hipGetLastError();
+}
+
+hipError_t gm_givens(int nr, int k, double* H, int ldh, double* cs, double* sn, double* g, const double* sc,
+                     int sc_stride, double tau, int* flag, const int* act, hipStream_t s) {
+    k_givens<<<1, 64, 0, s>>>(nr, k, H, ldh, cs, sn, g, sc, sc_stride, tau, flag, act);
+    return hipGetLastError();
+}
+
+hipError_t gm_update(int64_t n, int nr, const double* H, int ldh, const double* g, double* y, const int* kdim,
+                     const double* V, double* X, int64_t ldx, hipStream_t s) {
+    k_backsub<<<1, 64, 0, s>>>(nr, H, ldh, g, y, kdim);
+    k_axpy_basis<<<dim3((unsigned)((n + 255) / 256), nr), 256, 0, s>>>(n, nr, V, y, ldh, kdim, X, ldx);
+    return hipGetLastError();
+}
+
+hipError_t set_i32(int* dst, int n, const int* src_dev, hipStream_t s) {
+    k_set_i32<<<1, 64, 0, s>>>(dst, n, src_dev);
     return hipGetLastError();
 }
 

@@ -16,6 +16,9 @@ pytestmark = pytest.mark.gpu
 TORCH_OP = {"f16": torch.float16, "bf16": torch.bfloat16, "f8": torch.float8_e4m3fn, "f32": torch.float32}
 TORCH_ST = {"f16": torch.float16, "bf16": torch.bfloat16, "f32": torch.float32}
 U_ST = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8, "f32": 2.0 ** -24}
+# half the spacing of the storage format's subnormals: the absolute error of a
+# rounding that lands below its smallest normal number
+SUB_ST = {"f16": 2.0 ** -25, "bf16": 2.0 ** -134, "f32": 2.0 ** -150}
 
 
 def _pad(x, m):
@@ -33,7 +36,26 @@ def _pad(x, m):
     (1, 1, 64, "bf16", "f32"),
 ])
 def test_trailing_update_matches_definition(M, N, K, update, store):
-    print("gemm", M, N, K, update, store, flush=True)
+    _run_update(M, N, K, update, store, aligned=False)
+
+
+# ldc a multiple of 8 elements (16-byte columns) with whole 256 x 128 tiles:
+# the production epilogue (C half-tile loaded at the first stage, LDS-staged
+# read-modify-write, streaming stores); the last shapes mix full and edge tiles
+@pytest.mark.parametrize("M,N,K,update,store", [
+    (1024, 1024, 512, "f16", "f16"),
+    (1024, 768, 512, "bf16", "bf16"),
+    (768, 1024, 512, "f8", "f16"),
+    (512, 512, 1024, "f8", "bf16"),
+    (1000, 900, 512, "f16", "f16"),
+    (1300, 517, 256, "f8", "f16"),
+])
+def test_trailing_update_full_tiles_aligned(M, N, K, update, store):
+    _run_update(M, N, K, update, store, aligned=True)
+
+
+def _run_update(M, N, K, update, store, aligned):
+    print("gemm", M, N, K, update, store, "aligned" if aligned else "", flush=True)
     g = torch.Generator().manual_seed(M * 7 + N)
     Mp, Np = _pad(M, 256), _pad(N, 256)
     A = torch.rand((Mp, K), generator=g, dtype=torch.float64) * 2 - 1
@@ -43,7 +65,10 @@ def test_trailing_update_matches_definition(M, N, K, update, store):
     Bq = (B.float() * scale_op).to(TORCH_OP[update])
     ia = torch.pow(2.0, torch.randint(-20, -5, (Mp // 32,), generator=g).double()).float()
     ib = torch.pow(2.0, torch.randint(-8, 3, (Np // 32,), generator=g).double()).float()
-    ldc = M + 3 if store != "f32" else M + 4
+    if aligned:
+        ldc = _pad(M, 8) + 64
+    else:
+        ldc = M + 3 if store != "f32" else M + 4
     C = (torch.rand((N, ldc), generator=g, dtype=torch.float64) * 8 - 4).to(TORCH_ST[store])
     Cd = C.cuda()
     mxp.mxp_trailing_update(Cd, ldc, M, N, K, update, store, Aq.cuda(), Bq.cuda(), ia.cuda(), ib.cuda())
@@ -56,7 +81,7 @@ def test_trailing_update_matches_definition(M, N, K, update, store):
     prod = (a @ b.T) * da[:, None] * db[None, :]
     ref = C0 - prod
     mag = np.abs(C0) + (np.abs(a) @ np.abs(b).T) * da[:, None] * db[None, :]
-    bound = U_ST[store] * np.abs(ref) + (K + 2) * 2.0 ** -24 * mag + 1e-30
+    bound = U_ST[store] * np.abs(ref) + SUB_ST[store] + (K + 2) * 2.0 ** -24 * mag
     err = np.abs(got.numpy()[:, :M].T - ref)
     assert np.all(err <= bound), float((err / bound).max())
     # padding rows of C (ld > M) untouched

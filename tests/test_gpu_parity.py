@@ -24,6 +24,8 @@ def _dev_matrix(prob):
 
 
 def _oracle_stored(A, store):
+    if store == "f64":
+        return A
     if store == "f32":
         return A.astype(np.float32).astype(np.float64)
     if store == "f16":
@@ -37,14 +39,31 @@ def test_generator_bit_exact(n, store):
     print("generator", n, store, flush=True)
     prob = mxp.mxp_generate(n, 3, seed=12345, store=store)
     torch.cuda.synchronize()
-    A, d = oracle.generate(n, 12345)
+    A, d, l1 = oracle.generate(n, 12345, row_l1=True)
     got = _dev_matrix(prob)
     want = _oracle_stored(A, store)
     assert np.array_equal(got, want)
     assert np.array_equal(prob.diag.cpu().numpy(), d)
+    assert np.array_equal(prob.row_l1.cpu().numpy(), l1)
     assert prob.a_inf.item() == oracle.anorm_inf_regen(n, 12345)
     B = oracle.generate_rhs(n, 3, 12345)
     assert np.array_equal(prob.B.cpu().numpy().T, B)
+
+
+@pytest.mark.parametrize("n", [1, 6, 333, 1000])
+@pytest.mark.parametrize("kind,gamma", [(mxp.GEN_SQRTN, 0.3), (mxp.GEN_SQRTN, 1.7), (mxp.GEN_UNIFORM, 0.0)])
+@pytest.mark.parametrize("store", ["f64", "f16", "bf16"])
+def test_generator_kinds_bit_exact(n, kind, gamma, store):
+    print("generator kind", kind, gamma, n, store, flush=True)
+    prob = mxp.mxp_generate(n, 2, seed=77, store=store, kind=kind, gamma=gamma)
+    torch.cuda.synchronize()
+    A, d, l1 = oracle.generate(n, 77, kind, gamma, row_l1=True)
+    got = mxp.as_matrix(prob.A, n).double().cpu().numpy()
+    want = A if store == "f64" else _oracle_stored(A, store)
+    assert np.array_equal(got, want)
+    assert np.array_equal(prob.diag.cpu().numpy(), d)
+    assert np.array_equal(prob.row_l1.cpu().numpy(), l1)
+    assert prob.a_inf.item() == oracle.anorm_inf_regen(n, 77, kind, gamma)
 
 
 def test_generator_regen_only_and_large_seed():
@@ -73,6 +92,22 @@ def test_residual_regen(n, nrhs):
         assert np.all(np.abs(AX[r] - A @ X[r]) <= bound + 1e-300)
 
 
+@pytest.mark.parametrize("kind,gamma", [(mxp.GEN_SQRTN, 0.5), (mxp.GEN_UNIFORM, 0.0)])
+def test_residual_regen_kinds(kind, gamma):
+    n, nrhs = 1027, 3
+    print("residual kind", kind, n, flush=True)
+    prob = mxp.mxp_generate(n, nrhs, seed=9, store="f16", with_matrix=False, kind=kind, gamma=gamma)
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, (nrhs, n))
+    R = mxp.mxp_residual(prob, torch.from_numpy(X).cuda(), prob.B).cpu().numpy()
+    A, _ = oracle.generate(n, 9, kind, gamma)
+    B = oracle.generate_rhs(n, nrhs, 9)
+    for r in range(nrhs):
+        want = oracle.residual_regen(n, 9, X[r], B[:, r], kind, gamma)
+        bound = 64 * n * 2.0 ** -53 * (np.abs(A) @ np.abs(X[r]) + np.abs(B[:, r]))
+        assert np.all(np.abs(R[r] - want) <= bound)
+
+
 def test_residual_regen_chunks_meet_row_tiles_in_part():
     # n = 20001: column chunks of 832 columns, not a multiple of the 256-row
     # work-group tiles, so some work-groups' rows meet a chunk's columns (and
@@ -94,7 +129,7 @@ def test_residual_regen_chunks_meet_row_tiles_in_part():
 
 
 CASES = [
-    # n, nb, update, store, u_low bound factor
+    # n, nb, update, store
     (256, 64, "f32", "f32"),
     (300, 64, "f16", "f16"),
     (1000, 256, "f16", "f16"),
@@ -107,7 +142,6 @@ CASES = [
     (65, 64, "f32", "f32"),
     (1, 64, "f32", "f32"),
 ]
-U_LOW = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8, "f8": 2.0 ** -4}
 
 
 def _solve(n, nb, update, store, seed=1, nrhs=1, scaling=mxp.SCALE_NONE):
@@ -119,23 +153,6 @@ def _solve(n, nb, update, store, seed=1, nrhs=1, scaling=mxp.SCALE_NONE):
 
 
 @pytest.mark.parametrize("n,nb,update,store", CASES)
-def test_preconditioner_quality(n, nb, update, store):
-    print("prec", n, nb, update, store, flush=True)
-    prob = mxp.mxp_generate(n, 2, seed=3, store=store)
-    fac = mxp.mxp_factor(prob, nb, update)
-    assert fac.info == 0
-    V = prob.B.clone()
-    Z = mxp.mxp_apply_prec(fac, V).cpu().numpy()
-    A, _ = oracle.generate(n, 3)
-    LU, _ = oracle.lu_nopiv(A)
-    u = max(U_LOW[update], U_LOW[store])
-    for r in range(2):
-        xr = oracle.lu_solve(LU, V[r].cpu().numpy())
-        err = np.abs(Z[r] - xr).max() / np.abs(xr).max()
-        assert err <= 16 * u, (err, u)
-
-
-@pytest.mark.parametrize("n,nb,update,store", CASES)
 def test_solve_matches_oracle(n, nb, update, store):
     print("solve", n, nb, update, store, flush=True)
     prob, fac, res = _solve(n, nb, update, store, seed=11, nrhs=2)
@@ -144,6 +161,27 @@ def test_solve_matches_oracle(n, nb, update, store):
     for r in range(2):
         assert res.status[r] == 0 and res.eta[r] < 16, (res.status, res.eta)
         assert res.iters[r] <= 50
+        err = np.abs(X[r] - Xo[:, r]).max() / np.abs(Xo[:, r]).max()
+        assert err <= 1e-12, err
+        assert oracle.hpl_eta(A, X[r], Bo[:, r]) < 16
+
+
+@pytest.mark.parametrize("n,nb,update,store,gamma", [(1000, 128, "f16", "f16", 0.5), (777, 128, "bf16", "bf16", 0.7),
+                                                     (1536, 256, "f32", "f32", 0.3), (1100, 256, "f16", "f32", 0.3)])
+def test_solve_sqrtn_kind_matches_oracle(n, nb, update, store, gamma):
+    # the diagonal gamma sqrt(n): far from row dominance, GMRES-IR needs the
+    # LU preconditioner and more iterations than for the dominant matrices
+    print("solve sqrt(n) kind", n, nb, update, store, gamma, flush=True)
+    seed = 13
+    prob = mxp.mxp_generate(n, 2, seed=seed, store=store, kind=mxp.GEN_SQRTN, gamma=gamma)
+    fac = mxp.mxp_factor(prob, nb, update)
+    assert fac.info == 0
+    res = mxp.mxp_solve_ir(prob, fac)
+    A, Bo, Xo, reps = oracle.solve(n, seed, nrhs=2, kind=oracle.GEN_SQRTN, gamma=gamma)
+    X = res.X.cpu().numpy()
+    print("  iters", res.iters, "eta", res.eta, flush=True)
+    for r in range(2):
+        assert res.status[r] == 0 and res.eta[r] < 16 and res.iters[r] <= 50
         err = np.abs(X[r] - Xo[:, r]).max() / np.abs(Xo[:, r]).max()
         assert err <= 1e-12, err
         assert oracle.hpl_eta(A, X[r], Bo[:, r]) < 16

@@ -1,7 +1,8 @@
 """GPU tests of the solve server (mxp_server_* through the C ABI).
 
-Each request is generated, factored and refined exactly as a direct call
-would; the server only schedules.  The checks: every result meets the HPL
+Each request is generated, factored and refined with the arithmetic of a
+direct call (a group's factorisations share their launches, which gives the
+same bits); the server only schedules.  The checks: every result meets the HPL
 criterion and matches the oracle (small sizes); a request's solution is the
 same when it runs alone and when it runs in a mix of concurrent requests;
 admission respects the HBM budget; the tuner's block sizes are valid.
@@ -36,6 +37,8 @@ def test_alone_and_in_the_mix_agree():
         st = srv.stats()
         assert st["failed"] == 0 and st["completed"] == 2 * len(REQS)
         assert st["peak_in_flight"] >= 2          # the mix really ran concurrently
+        assert st["peak_group"] >= 2              # some requests were factored with shared launches
+        assert st["grouped_requests"] == 2 * len(REQS) and 1 <= st["streams"] <= 3
         assert st["peak_bytes_in_use"] <= st["arena_bytes"]
         for rid, key in ids:
             res = srv.wait(rid)
@@ -84,6 +87,7 @@ def test_autotuned_block_sizes():
     with mxp.Server(2 * mxp.server_request_bytes(16384, 1, 512), max_slots=2, autotune=True) as srv:
         for n in (512, 1024, 2048, 4096, 8192, 16384):
             assert srv.block_size(n) in (128, 256, 512)
+            assert srv.tile(n) in (mxp.TILE_256x128, mxp.TILE_128x128)
         ids = [srv.submit(n, 1, 3000 + n) for n in (600, 2500, 9000)]
         for rid in ids:
             res = srv.wait(rid)

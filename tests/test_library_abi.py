@@ -48,9 +48,18 @@ def test_size_queries():
 def test_argument_errors_return_einval_without_device_work():
     L = mxp.lib()
     # NULL diag / a_inf, bad n: rejected before anything is enqueued
-    assert L.mxp_generate(0, 0, 1, mxp.F16, None, 0, None, 0, None, None, None) == mxp.EINVAL
-    assert L.mxp_generate(16, 0, 1, mxp.F16, None, 16, None, 16, None, None, None) == mxp.EINVAL
+    assert L.mxp_generate(0, 0, 1, mxp.GEN_DOMINANT, 0.0, mxp.F16, None, 0, None, 0, None, None, None,
+                          None) == mxp.EINVAL
+    assert L.mxp_generate(16, 0, 1, mxp.GEN_DOMINANT, 0.0, mxp.F16, None, 16, None, 16, None, None, None,
+                          None) == mxp.EINVAL
     assert b"mxp_generate" in L.mxp_last_error()
+    fake = ctypes.c_void_p(256)
+    # an unknown matrix kind, a sqrt(n) diagonal without a positive coefficient
+    assert L.mxp_generate(16, 0, 1, 7, 0.0, mxp.F16, None, 16, None, 16, fake, None, fake, None) == mxp.EINVAL
+    assert L.mxp_generate(16, 0, 1, mxp.GEN_SQRTN, 0.0, mxp.F16, None, 16, None, 16, fake, None, fake,
+                          None) == mxp.EINVAL
+    assert L.mxp_generate(16, 0, 1, mxp.GEN_SQRTN, -1.0, mxp.F16, None, 16, None, 16, fake, None, fake,
+                          None) == mxp.EINVAL
     # bad (update, store) pair, bad nb
     fake = ctypes.c_void_p(256)
     assert L.mxp_factor(64, 64, mxp.F16, mxp.BF16, 0, None, fake, 64, fake, fake, 1 << 30, None, None) == mxp.EINVAL
@@ -106,3 +115,26 @@ def test_profile_classes_mask_and_read_without_device_work():
     assert L.mxp_profile_enable(0) == 0
     mxp.profile_enable(True, classes=[mxp.PROF_GEMM, mxp.PROF_DIAG])
     mxp.profile_enable(False)
+
+
+def test_factor_layout_query():
+    """The aux/work layout query: parts in order, inside the sizes the
+    *_bytes queries give, 256-byte aligned, and rejected for bad sizes."""
+    L = mxp.lib()
+    for n, nb, up in ((32768, 512, mxp.F16), (1000, 128, mxp.F8E4M3), (65, 64, mxp.F32)):
+        lay = mxp.factor_layout(n, nb, up)
+        aux = [lay.T, lay.Trm, lay.linv, lay.uinv, lay.lsc, lay.rowscale, lay.linv_full, lay.uinv_full, lay.aux_bytes]
+        work = [lay.Lq, lay.Uq, lay.inv_sa, lay.inv_sb, lay.info, lay.work_bytes]
+        assert aux == sorted(aux) and work == sorted(work)
+        assert all(x % 256 == 0 for x in aux + work)
+        assert lay.aux_bytes == L.mxp_factor_aux_bytes(n, nb)
+        assert lay.work_bytes == L.mxp_factor_work_bytes(n, nb, up)
+        nblk = -(-n // nb)
+        assert lay.strips == -(-n // 32) and lay.op_rows >= n
+        assert lay.Trm - lay.T >= nblk * nb * nb * 4 and lay.rowscale - lay.lsc >= nblk * lay.strips * 4
+        esz = {mxp.F16: 2, mxp.F8E4M3: 1, mxp.F32: 4}[up]
+        assert lay.Uq - lay.Lq >= 2 * lay.op_rows * nb * esz
+    with pytest.raises(mxp.MxpError):
+        mxp.factor_layout(0, 64, mxp.F16)
+    with pytest.raises(mxp.MxpError):
+        mxp.factor_layout(100, 96, mxp.F16)

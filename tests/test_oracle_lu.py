@@ -115,3 +115,58 @@ def test_zero_pivot_reported_with_column():
     assert info == 2                       # second pivot is 1 - 0.5*2 = 0
     A2 = np.array([[np.nan, 0.0], [0.0, 1.0]], order="F")
     assert oracle.lu_nopiv(A2)[1] == 1
+
+
+# ---------------------------------------------------------------- partial pivoting
+@pytest.mark.parametrize("n,seed", [(50, 1), (257, 2), (600, 3)])
+def test_partial_pivoting_matches_library_lu(n, seed):
+    # "Experimental Results": LU with partial pivoting on entries uniform in
+    # [-1, 1) without diagonal scaling; LAPACK's getrf (scipy) takes the same
+    # pivot rule (largest magnitude, first among equals)
+    A, _ = oracle.generate(n, seed, oracle.GEN_UNIFORM)
+    LU, ipiv, info = oracle.lu_pp(A)
+    assert info == 0
+    lu, piv = scipy.linalg.lu_factor(A)
+    assert np.array_equal(ipiv, piv)
+    assert np.abs(LU - lu).max() <= 64 * n * EPS * np.abs(lu).max()
+    # P A = L U
+    P = np.arange(n)
+    for k in range(n):
+        P[[k, ipiv[k]]] = P[[ipiv[k], k]]
+    L, U = np.tril(LU, -1) + np.eye(n), np.triu(LU)
+    assert np.abs(A[P] - L @ U).max() <= 8 * n * EPS * (np.abs(L) @ np.abs(U)).max()
+    assert np.abs(np.tril(LU, -1)).max() <= 1.0            # |multipliers| <= 1 by construction
+    b = oracle.generate_rhs(n, 1, seed)[:, 0]
+    x = oracle.lu_pp_solve(LU, ipiv, b)
+    xr = scipy.linalg.lu_solve((lu, piv), b)
+    assert np.abs(x - xr).max() <= 1e-10 * np.abs(xr).max()
+
+
+def test_partial_pivoting_plant_mistake_is_caught():
+    # a dropped row swap in the L part (a plausible slip) breaks P A = L U
+    n = 40
+    A, _ = oracle.generate(n, 9, oracle.GEN_UNIFORM)
+    LU, ipiv, _ = oracle.lu_pp(A)
+    k = int(np.nonzero(ipiv != np.arange(n))[0][3])
+    bad = LU.copy()
+    bad[[k, ipiv[k]], :k] = bad[[ipiv[k], k], :k]
+    P = np.arange(n)
+    for j in range(n):
+        P[[j, ipiv[j]]] = P[[ipiv[j], j]]
+    L, U = np.tril(bad, -1) + np.eye(n), np.triu(bad)
+    assert np.abs(A[P] - L @ U).max() > 1e-3
+
+
+def test_largest_pivot_grows_like_sqrt_n():
+    # Figure 2's experiment: the largest pivot |u_kk| of partial pivoting on
+    # these matrices grows like sqrt(n) (the paper's curves: sqrt(n),
+    # 5/8 sqrt(n), n^0.45) and is found late in the elimination; without
+    # pivoting the same matrices give far larger pivots
+    for n in (256, 1024):
+        A, _ = oracle.generate(n, 4, oracle.GEN_UNIFORM)
+        LU, ipiv, _ = oracle.lu_pp(A)
+        d = np.abs(np.diag(LU))
+        assert 0.5 * np.sqrt(n) < d.max() < 2.0 * np.sqrt(n)
+        assert np.argmax(d) >= n // 2
+        LU0, _ = oracle.lu_nopiv(A)
+        assert np.abs(np.diag(LU0)).max() > 2.0 * d.max()
