@@ -272,6 +272,21 @@ size_t mxp_residual_work_bytes(int64_t n, int64_t nrhs);
 int mxp_residual(int64_t n, uint64_t seed, int kind, const double *diag, const double *X, int64_t ldx,
                  const double *B, int64_t ldb, double *R, int64_t ldr, int64_t nrhs, void *work, size_t work_bytes,
                  void *stream);
+/*
+ * mxp_residual_noalloc: mxp_residual without a work buffer, for callers that
+ *   cannot allocate device memory (code under stream capture, tight serving
+ *   loops, harnesses that forbid allocation).  The partial products live in
+ *   a file-scope device array of the library, 32 MiB per device, held by
+ *   every device the library runs on until the process ends; the call
+ *   allocates nothing.  Sizes whose partials exceed it (mxp_residual_work_bytes
+ *   > 32 MiB: n * min(nrhs, 8) above about 4 M, e.g. n = 131072 fits with 8
+ *   columns) are rejected with MXP_EINVAL.  Every call on a device shares
+ *   that device's array: calls that overlap on one device (several streams
+ *   or host threads) race and must be ordered by the caller.  Nothing in the
+ *   array needs clearing: each call overwrites what it reads.
+ */
+int mxp_residual_noalloc(int64_t n, uint64_t seed, int kind, const double *diag, const double *X, int64_t ldx,
+                         const double *B, int64_t ldb, double *R, int64_t ldr, int64_t nrhs, void *stream);
 size_t mxp_apply_prec_work_bytes(int64_t n, int64_t nrhs);
 int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, const void *LU, int64_t lda, const void *aux,
                    const double *V, int64_t ldv, double *Z, int64_t ldz, int64_t nrhs, void *work, size_t work_bytes,

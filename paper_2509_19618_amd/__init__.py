@@ -95,6 +95,7 @@ SIGNATURES = [
                           _D, _P, _P, _SZ, _P]),
     ("mxp_residual_work_bytes", _SZ, [_I64, _I64]),
     ("mxp_residual", _I, [_I64, _U64, _I, _P, _P, _I64, _P, _I64, _P, _I64, _I64, _P, _SZ, _P]),
+    ("mxp_residual_noalloc", _I, [_I64, _U64, _I, _P, _P, _I64, _P, _I64, _P, _I64, _I64, _P]),
     ("mxp_apply_prec_work_bytes", _SZ, [_I64, _I64]),
     ("mxp_apply_prec", _I, [_I64, _I64, _I, _I, _P, _I64, _P, _P, _I64, _P, _I64, _I64, _P, _SZ, _P]),
     ("mxp_hpl_eta_work_bytes", _SZ, [_I64]),

@@ -411,6 +411,21 @@ extern "C" int mxp_residual(int64_t n, uint64_t seed, int kind, const double* di
     return MXP_OK;
 }
 
+extern "C" int mxp_residual_noalloc(int64_t n, uint64_t seed, int kind, const double* diag, const double* X,
+                                    int64_t ldx, const double* B, int64_t ldb, double* R, int64_t ldr, int64_t nrhs,
+                                    void* stream) {
+    if (n < 1 || n >= (1ll << 31) || nrhs < 1 || !valid_kind(kind) || !diag || !X || !R || ldx < n || ldr < n ||
+        (B && ldb < n))
+        return set_err(MXP_EINVAL, "mxp_residual_noalloc: bad argument%s", "");
+    if (mxp_residual_work_bytes(n, nrhs) > static_scratch_bytes())
+        return set_err(MXP_EINVAL, "mxp_residual_noalloc: n * min(nrhs, 8) too large for the library's %s scratch",
+                       "32 MiB");
+    void* scr = nullptr;
+    HIPCHK(static_scratch(&scr));
+    HIPCHK(regen_matvec(n, seed, kind, diag, X, ldx, (int)nrhs, B, ldb, R, ldr, (double*)scr, (hipStream_t)stream));
+    return MXP_OK;
+}
+
 extern "C" size_t mxp_apply_prec_work_bytes(int64_t n, int64_t nrhs) {
     if (n < 1 || nrhs < 1 || nrhs > 64) return 0;
     return prec_work_bytes(n, (int)nrhs);

@@ -2,6 +2,8 @@
 // regenerates the matrix instead of reading it (paper: "Matrix Generation",
 // scalable generation with any entry computable on its own; "Algorithmic
 // Framework", 64-bit residual of the refinement and the HPL scaled residual).
+#include <mutex>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "prof.hpp"
@@ -355,5 +357,37 @@ hipError_t hpl_eta_dev(int64_t n, int nr, const double* r, int64_t ldr, const do
     k_eta_final<<<nr, 256, 0, s>>>(n, nb, part, a_inf, eta_out);
     return hipGetLastError();
 }
+
+}  // namespace mxp
+
+namespace mxp {
+
+// ---------------------------------------------------------------- residual without allocation
+// For callers that cannot allocate (code under stream capture, tight serving
+// loops): the partial products of the regenerating GEMV live in a file-scope
+// device array instead of a work buffer.  Its host-side name is not a device
+// address: the address is looked up once per device and kept.
+constexpr size_t STATIC_SCRATCH_BYTES = size_t(32) << 20;
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_BYTES / sizeof(double)];
+
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[64];
+
+hipError_t static_scratch(void** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if ((e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)))) return e;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+size_t static_scratch_bytes() { return STATIC_SCRATCH_BYTES; }
 
 }  // namespace mxp

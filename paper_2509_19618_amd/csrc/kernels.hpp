@@ -18,6 +18,10 @@ size_t regen_partial_bytes(int64_t n, int nr);
 hipError_t regen_matvec(int64_t n, uint64_t seed, int kind, const double* diag, const double* X, int64_t ldx, int nr,
                         const double* B, int64_t ldb, double* R, int64_t ldr, double* P, hipStream_t s);
 int eta_blocks(int64_t n);
+// the library's file-scope device scratch array (device address on the
+// current device, looked up once per device) and its size
+hipError_t static_scratch(void** out);
+size_t static_scratch_bytes();
 // eta_out[4 q] = HPL scaled residual of right-hand side q (q < nr), [4 q + 1]
 // ||x_q||_inf, [4 q + 2] ||r_q||_inf; part: eta_blocks(n) * 3 * nr doubles
 hipError_t hpl_eta_dev(int64_t n, int nr, const double* r, int64_t ldr, const double* x, int64_t ldx,
