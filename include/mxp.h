@@ -203,10 +203,10 @@ int mxp_factor_group(int count, const mxp_factor_item *items, int update, int st
  *                   stored value is s * L), 1 where no scaling is applied
  *         rowscale  FP64 n: the row scaling S (1 without equilibration)
  *         linv_full/uinv_full FP32 nblk x nb x nb: L11^-1 and U11^-1
- *   work: Lq/Uq     two alternating sets of op_rows x nb update operands
- *                   (row-major: K contiguous), set (k/nb) & 1 for step k;
+ *   work: Lq/Uq     four sets of op_rows x nb update operands
+ *                   (row-major: K contiguous), set (k/nb) & 3 for step k;
  *                   row 0 of a set is the first row after the step's block
- *         inv_sa/inv_sb two sets of op_rows/32 FP32 factors 1/s per
+ *         inv_sa/inv_sb four sets of op_rows/32 FP32 factors 1/s per
  *                   32-row strip of Lq / Uq
  *         info      unsigned 64-bit: first failing pivot column, ~0 if none
  * Returns MXP_EINVAL for sizes mxp_factor would reject.
@@ -303,6 +303,19 @@ int mxp_apply_prec(int64_t n, int64_t nb, int update, int store, const void *LU,
  */
 int mxp_trailing_update(int64_t M, int64_t N, int64_t K, int update, int store, void *C, int64_t ldc,
                         const void *Aq, const void *Bq, const float *inv_sa, const float *inv_sb, void *stream);
+/*
+ * mxp_trailing_update2: the updates of two consecutive block steps in one
+ * pass (how mxp_factor updates everything beyond the next block column),
+ * C <- C - [diag(inv_sa1) Aq1 Bq1^T diag(inv_sb1) + diag(inv_sa2) Aq2 Bq2^T diag(inv_sb2)]:
+ * each operand pair as for mxp_trailing_update (K1 resp. K2 values per row,
+ * K * element size a multiple of 128 bytes); the factors must be powers of
+ * two.  The sum is accumulated in FP32 (the first step's partial sums are
+ * brought to the second step's scale, exactly) and rounded to the storage
+ * format once.  Asynchronous.
+ */
+int mxp_trailing_update2(int64_t M, int64_t N, int64_t K1, int64_t K2, int update, int store, void *C, int64_t ldc,
+                         const void *Aq1, const void *Bq1, const float *inv_sa1, const float *inv_sb1,
+                         const void *Aq2, const void *Bq2, const float *inv_sa2, const float *inv_sb2, void *stream);
 size_t mxp_hpl_eta_work_bytes(int64_t n);
 int mxp_hpl_eta(int64_t n, uint64_t seed, int kind, const double *diag, const double *a_inf, const double *x,
                 const double *b, double *eta, void *work, size_t work_bytes, void *stream);

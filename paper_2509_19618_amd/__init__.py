@@ -101,6 +101,7 @@ SIGNATURES = [
     ("mxp_hpl_eta_work_bytes", _SZ, [_I64]),
     ("mxp_hpl_eta", _I, [_I64, _U64, _I, _P, _P, _P, _P, _P, _P, _SZ, _P]),
     ("mxp_trailing_update", _I, [_I64, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P]),
+    ("mxp_trailing_update2", _I, [_I64, _I64, _I64, _I64, _I, _I, _P, _I64, _P, _P, _P, _P, _P, _P, _P, _P, _P]),
     ("mxp_lu64_work_bytes", _SZ, [_I64]),
     ("mxp_trailing_update64", _I, [_I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64, _P]),
     ("mxp_lu64_factor", _I, [_I64, _P, _I64, _P, _I, _P, _SZ, _P, _P]),
@@ -331,6 +332,16 @@ def mxp_trailing_update(C: torch.Tensor, ldc: int, M: int, N: int, K: int, updat
     """C <- C - diag(inv_sa) Aq Bq^T diag(inv_sb) (see include/mxp.h)."""
     _check(lib().mxp_trailing_update(M, N, K, dtype_code(update), dtype_code(store), _ptr(C), ldc, _ptr(Aq),
                                      _ptr(Bq), _ptr(inv_sa), _ptr(inv_sb), _stream(stream)))
+
+
+def mxp_trailing_update2(C: torch.Tensor, ldc: int, M: int, N: int, K1: int, K2: int, update, store,
+                         Aq1: torch.Tensor, Bq1: torch.Tensor, inv_sa1: torch.Tensor, inv_sb1: torch.Tensor,
+                         Aq2: torch.Tensor, Bq2: torch.Tensor, inv_sa2: torch.Tensor, inv_sb2: torch.Tensor,
+                         stream=None) -> None:
+    """The updates of two block steps in one pass (see include/mxp.h)."""
+    _check(lib().mxp_trailing_update2(M, N, K1, K2, dtype_code(update), dtype_code(store), _ptr(C), ldc, _ptr(Aq1),
+                                      _ptr(Bq1), _ptr(inv_sa1), _ptr(inv_sb1), _ptr(Aq2), _ptr(Bq2),
+                                      _ptr(inv_sa2), _ptr(inv_sb2), _stream(stream)))
 
 
 # ------------------------------------------------------------------ FP64 LU

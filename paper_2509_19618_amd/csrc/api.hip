@@ -486,6 +486,25 @@ extern "C" int mxp_trailing_update(int64_t M, int64_t N, int64_t K, int update, 
     return MXP_OK;
 }
 
+extern "C" int mxp_trailing_update2(int64_t M, int64_t N, int64_t K1, int64_t K2, int update, int store, void* C,
+                                    int64_t ldc, const void* Aq1, const void* Bq1, const float* inv_sa1,
+                                    const float* inv_sb1, const void* Aq2, const void* Bq2, const float* inv_sa2,
+                                    const float* inv_sb2, void* stream) {
+    if (M < 0 || N < 0 || K1 < 1 || K1 > 4096 || K2 < 1 || K2 > 4096 || ldc < (M > 1 ? M : 1) ||
+        !valid_pair(update, store) || (K1 * dtype_bytes(update)) % 128 || (K2 * dtype_bytes(update)) % 128 ||
+        (M > 0 && N > 0 && (!C || !Aq1 || !Bq1 || !inv_sa1 || !inv_sb1 || !Aq2 || !Bq2 || !inv_sa2 || !inv_sb2)))
+        return set_err(MXP_EINVAL, "mxp_trailing_update2: bad argument%s", "");
+    if (M == 0 || N == 0) return MXP_OK;
+    GemmCall c{C, ldc, M, N, (int)K1, Aq1, Bq1, inv_sa1, inv_sb1};
+    c.K2 = (int)K2;
+    c.Aq2 = Aq2; c.Bq2 = Bq2; c.inv_sa2 = inv_sa2; c.inv_sb2 = inv_sb2;
+    hipEvent_t pt = prof::begin(prof::GEMM, (hipStream_t)stream);
+    HIPCHK(gemm_group(update, store, GEMM_TILE_256, &c, 1, (hipStream_t)stream));
+    prof::end(pt, prof::GEMM, (hipStream_t)stream, 2.0 * M * (double)N * (K1 + K2),
+              2.0 * M * (double)N * dtype_bytes(store) + (double)(M + N) * (K1 + K2) * dtype_bytes(update));
+    return MXP_OK;
+}
+
 // ------------------------------------------------------------------ FP64 LU
 extern "C" size_t mxp_lu64_work_bytes(int64_t n) {
     if (n < 1 || n >= (1ll << 31)) return 0;

@@ -10,6 +10,13 @@
 // The accumulators start at zero and hold sum Aq Bq^T in FP32; the result
 // C - acc * (inv_sa inv_sb) is rounded once to the storage format.
 //
+// An update may have a second K segment: the operands of the next block step
+// with factors of their own (the updates of two consecutive steps merged,
+// which halves the C traffic per flop).  At the segment boundary each 32 x 32
+// accumulator block is multiplied by (inv_sa inv_sb) / (inv_sa2 inv_sb2), a
+// power of two (exact), the second segment accumulates onto it, and the
+// result is C - acc * (inv_sa2 inv_sb2), rounded once.
+//
 // Work-groups are dispatched round-robin over the 8 XCDs; the tile order
 // gives every XCD a contiguous range of tiles, walked in groups of 8 tile
 // rows so that the operand panels in flight on an XCD fit its L2.
@@ -184,10 +191,14 @@ struct GemmOne {
     const char* Bq;
     const float* inv_sa;
     const float* inv_sb;
-    int K, tiles_m, tiles_n, tile_end, vec_ok, pad;
+    const char* Aq2;                 // second segment (K2 > 0)
+    const char* Bq2;
+    const float* inv_sa2;
+    const float* inv_sb2;
+    int K, K2, tiles_m, tiles_n, tile_end, vec_ok;
 };
 struct GemmGroup {
-    GemmOne g[GEMM_GROUP_MAX];
+    GemmOne g[GEMM_DESC_MAX];
     int count, per_xcd;
 };
 
@@ -229,9 +240,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(const GemmGroup grp) {
     const GemmOne& G = grp.g[d];
     CT* C = (CT*)G.C;
     const int64_t ldc = G.ldc, M = G.M, N = G.N;
-    const int K = G.K, tiles_m = G.tiles_m, tiles_n = G.tiles_n, vec_ok = G.vec_ok;
-    const float* __restrict__ inv_sa = G.inv_sa;
-    const float* __restrict__ inv_sb = G.inv_sb;
+    const int tiles_m = G.tiles_m, tiles_n = G.tiles_n, vec_ok = G.vec_ok;
+    // the epilogue's factors: those of the last segment
+    const float* __restrict__ inv_sa = G.K2 ? G.inv_sa2 : G.inv_sa;
+    const float* __restrict__ inv_sb = G.K2 ? G.inv_sb2 : G.inv_sb;
     const int lin = glin - (d > 0 ? grp.g[d - 1].tile_end : 0);
     const int group_size = GGROUP * tiles_n;
     const int first_m = (lin / group_size) * GGROUP;
@@ -240,27 +252,35 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(const GemmGroup grp) {
     const int tn = (lin % group_size) / gm;
     const int64_t row0 = (int64_t)tm * TMv, col0 = (int64_t)tn * TN;
     constexpr int eb = sizeof(typename Operand<OP>::T);
-    const int64_t Kbytes = (int64_t)K * eb;
-    const char* gA = G.Aq + row0 * Kbytes;
-    const char* gB = G.Bq + col0 * Kbytes;
-    const int nst = (int)(Kbytes / GBK);
+    const int64_t Kb1 = (int64_t)G.K * eb, Kb2 = (int64_t)G.K2 * eb;
+    const char* gA1 = G.Aq + row0 * Kb1;
+    const char* gB1 = G.Bq + col0 * Kb1;
+    const char* gA2 = G.K2 ? G.Aq2 + row0 * Kb2 : gA1;
+    const char* gB2 = G.K2 ? G.Bq2 + col0 * Kb2 : gB1;
+    const int nst1 = (int)(Kb1 / GBK);
+    const int nst = nst1 + (int)(Kb2 / GBK);
     const int lr = lane & 31, lh = lane >> 5;
     const int l_row = lane / GCH, l_pch = lane % GCH;
     auto issue = [&](int st) {
         const int buf = st % NBUF;
+        const bool s2 = st >= nst1;                           // wave-uniform
+        const char* gA = s2 ? gA2 : gA1;
+        const char* gB = s2 ? gB2 : gB1;
+        const int64_t Kbytes = s2 ? Kb2 : Kb1;
+        const int64_t ko = (int64_t)(s2 ? st - nst1 : st) * GBK;
 #pragma unroll
         for (int i = 0; i < NIA; ++i) {
             const int j = wave * NIA + i;                     // 1 KB slice of the stage
             const int row = j * RPI + l_row;
             const int lch = l_pch ^ (row & (GCH - 1));        // logical chunk stored at this lane's slot
-            dma16(gA + (int64_t)row * Kbytes + (int64_t)st * GBK + lch * 16, sA + buf * SA + j * 1024);
+            dma16(gA + (int64_t)row * Kbytes + ko + lch * 16, sA + buf * SA + j * 1024);
         }
 #pragma unroll
         for (int i = 0; i < NIB; ++i) {
             const int j = wave * NIB + i;
             const int row = j * RPI + l_row;
             const int lch = l_pch ^ (row & (GCH - 1));
-            dma16(gB + (int64_t)row * Kbytes + (int64_t)st * GBK + lch * 16, sB + buf * SB + j * 1024);
+            dma16(gB + (int64_t)row * Kbytes + ko + lch * 16, sB + buf * SB + j * 1024);
         }
     };
     f16v acc[NA][2];
@@ -296,6 +316,21 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(const GemmGroup grp) {
             for (int it = 0; it < NIT / 2; ++it) {
                 const int c = (wave * NIT + it) * CPI + lc;
                 xv[it] = __builtin_nontemporal_load((const i4v*)((const char*)(C + row0 + (col0 + c) * ldc) + lo));
+            }
+        }
+        if (st == nst1 && st > 0) {
+            // first stage of the second segment: the first segment's sums to its scale
+#pragma unroll
+            for (int a = 0; a < NA; ++a) {
+                const int64_t ra = (row0 + wm * WR + a * 32) / 32;
+                const float fa = G.inv_sa[ra] / G.inv_sa2[ra];
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    const int64_t cb = (col0 + wn * 64 + b * 32) / 32;
+                    const float f = fa * (G.inv_sb[cb] / G.inv_sb2[cb]);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) acc[a][b][r] *= f;
+                }
             }
         }
         const char* A0 = sA + (st % NBUF) * SA;
@@ -409,6 +444,8 @@ static hipError_t gemm_typed(const GemmCall* calls, int count, hipStream_t s) {
         g.C = c.C; g.ldc = c.ldc; g.M = c.M; g.N = c.N;
         g.Aq = (const char*)c.Aq; g.Bq = (const char*)c.Bq; g.inv_sa = c.inv_sa; g.inv_sb = c.inv_sb;
         g.K = c.K;
+        g.K2 = c.K2;
+        g.Aq2 = (const char*)c.Aq2; g.Bq2 = (const char*)c.Bq2; g.inv_sa2 = c.inv_sa2; g.inv_sb2 = c.inv_sb2;
         g.tiles_m = (int)((c.M + TMv - 1) / TMv);
         g.tiles_n = (int)((c.N + TN - 1) / TN);
         total += g.tiles_m * g.tiles_n;
@@ -416,7 +453,6 @@ static hipError_t gemm_typed(const GemmCall* calls, int count, hipStream_t s) {
         // vectorised C access needs 16-byte aligned columns
         g.vec_ok = ((c.ldc * (int64_t)sizeof(typename Store<ST>::T)) % 16 == 0 && (((uintptr_t)c.C) % 16) == 0) ? 1
                                                                                                                : 0;
-        g.pad = 0;
     }
     if (!used) return hipSuccess;
     grp.count = used;
@@ -426,9 +462,13 @@ static hipError_t gemm_typed(const GemmCall* calls, int count, hipStream_t s) {
 }
 
 hipError_t gemm_group(int update, int store, int tile, const GemmCall* calls, int count, hipStream_t s) {
-    if (count < 1 || count > GEMM_GROUP_MAX) return hipErrorInvalidValue;
-    for (int i = 0; i < count; ++i)
-        if ((calls[i].K * dtype_bytes(update)) % GBK) return hipErrorInvalidValue;
+    if (count < 1 || count > GEMM_DESC_MAX) return hipErrorInvalidValue;
+    for (int i = 0; i < count; ++i) {
+        const GemmCall& c = calls[i];
+        if (c.K < 1 || (c.K * dtype_bytes(update)) % GBK || c.K2 < 0 || (c.K2 * dtype_bytes(update)) % GBK ||
+            (c.K2 && (!c.Aq2 || !c.Bq2 || !c.inv_sa2 || !c.inv_sb2)))
+            return hipErrorInvalidValue;
+    }
 #define GCASE(U, S)                                                                                      \
     if (update == U && store == S)                                                                       \
         return tile == GEMM_TILE_128 ? gemm_typed<U, S, 128>(calls, count, s) : gemm_typed<U, S, 256>(calls, count, s)

@@ -65,9 +65,14 @@ WorkLayout work_layout(int64_t n, int64_t nb, int update);
 int dtype_bytes(int dt);
 
 // C (M x N, storage) <- C - diag(inv_sa) Aq Bq^T diag(inv_sb); Aq/Bq rows padded to 256.
+// With a second segment (K2 > 0: the operands of the next block step, with
+// their own factors) the update of both steps is accumulated in one pass:
+// C <- C - [diag(inv_sa) Aq Bq^T diag(inv_sb) + diag(inv_sa2) Aq2 Bq2^T diag(inv_sb2)],
+// rounded to the storage format once.
 // tile: the work-group tile of the update kernel (256 x 128 or 128 x 128).
 enum { GEMM_TILE_256 = 0, GEMM_TILE_128 = 1 };
-constexpr int GEMM_GROUP_MAX = 8;
+constexpr int GEMM_GROUP_MAX = 8;   // factorisations served by one grouped launch
+constexpr int GEMM_DESC_MAX = 16;   // update descriptors of one launch
 struct GemmCall {
     void* C;
     int64_t ldc, M, N;
@@ -76,12 +81,17 @@ struct GemmCall {
     const void* Bq;
     const float* inv_sa;
     const float* inv_sb;
+    int K2 = 0;
+    const void* Aq2 = nullptr;
+    const void* Bq2 = nullptr;
+    const float* inv_sa2 = nullptr;
+    const float* inv_sb2 = nullptr;
 };
 int gemm_tile_rows(int tile);
 hipError_t gemm_update(int update, int store, void* C, int64_t ldc, int64_t M, int64_t N, int K, const void* Aq,
                        const void* Bq, const float* inv_sa, const float* inv_sb, hipStream_t s,
                        int tile = GEMM_TILE_256);
-// up to GEMM_GROUP_MAX independent updates (same formats and tile) in one launch
+// up to GEMM_DESC_MAX independent updates (same formats and tile) in one launch
 hipError_t gemm_group(int update, int store, int tile, const GemmCall* calls, int count, hipStream_t s);
 // FP32 LU of the diagonal block A[k:k+kb, k:k+kb] (padded to kbp, a multiple
 // of 64, with the identity) by a few cooperating work-groups: T/Trm (ld ldt)
@@ -111,7 +121,7 @@ hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t 
 // update, rest of the trailing update)
 struct Lookahead {
     hipStream_t side = nullptr;
-    hipEvent_t ev_upd = nullptr, ev_cross = nullptr, ev_panel = nullptr;
+    hipEvent_t ev_upd = nullptr, ev_cross = nullptr, ev_next = nullptr, ev_panel = nullptr;
 };
 hipError_t lookahead_create(Lookahead* la);
 void lookahead_destroy(Lookahead* la);

@@ -60,10 +60,10 @@ WorkLayout work_layout(int64_t n, int64_t nb, int update) {
     int64_t rows = operand_rows(n);
     size_t eb = (size_t)dtype_bytes(update);
     size_t off = 0;
-    W.Lq = off; off = al256(off + 2 * (size_t)rows * nb * eb);     // two alternating sets
-    W.Uq = off; off = al256(off + 2 * (size_t)rows * nb * eb);
-    W.inv_sa = off; off = al256(off + 2 * (size_t)(rows / 32) * 4);
-    W.inv_sb = off; off = al256(off + 2 * (size_t)(rows / 32) * 4);
+    W.Lq = off; off = al256(off + 4 * (size_t)rows * nb * eb);     // four sets: two pairs of steps
+    W.Uq = off; off = al256(off + 4 * (size_t)rows * nb * eb);
+    W.inv_sa = off; off = al256(off + 4 * (size_t)(rows / 32) * 4);
+    W.inv_sb = off; off = al256(off + 4 * (size_t)(rows / 32) * 4);
     W.info = off; off = al256(off + 8);
     W.dsync = off; off = al256(off + (size_t)((n + nb - 1) / nb) * diag_sync_words() * 4);
     W.total = off;
@@ -517,11 +517,13 @@ hipError_t lookahead_create(Lookahead* la) {
     if ((e = hipStreamCreateWithFlags(&la->side, hipStreamNonBlocking))) return e;
     if ((e = hipEventCreateWithFlags(&la->ev_upd, hipEventDisableTiming))) return e;
     if ((e = hipEventCreateWithFlags(&la->ev_cross, hipEventDisableTiming))) return e;
+    if ((e = hipEventCreateWithFlags(&la->ev_next, hipEventDisableTiming))) return e;
     return hipEventCreateWithFlags(&la->ev_panel, hipEventDisableTiming);
 }
 
 void lookahead_destroy(Lookahead* la) {
     if (la->ev_panel) (void)hipEventDestroy(la->ev_panel);
+    if (la->ev_next) (void)hipEventDestroy(la->ev_next);
     if (la->ev_cross) (void)hipEventDestroy(la->ev_cross);
     if (la->ev_upd) (void)hipEventDestroy(la->ev_upd);
     if (la->side) (void)hipStreamDestroy(la->side);
@@ -572,7 +574,7 @@ static void trsm_desc(const FactorPlan& p, int64_t k, TrsmOne& g, int wg_begin) 
     const int kb = (int)(p.n - k < nb ? p.n - k : nb);
     const int64_t m = p.n - k - kb;
     const int64_t blk = k / nb;
-    const int set = (int)(blk & 1);
+    const int set = (int)(blk & 3);
     const int64_t opset = p.op_rows * nb, scset = p.op_rows / 32;
     const int nstrip = (int)(rup(m, 256) / SR);
     g.A = p.A; g.lda = p.lda; g.n = p.n; g.k = k; g.nb = nb; g.nstrip = nstrip;
@@ -589,17 +591,67 @@ static void trsm_desc(const FactorPlan& p, int64_t k, TrsmOne& g, int wg_begin) 
     g.inv_sb = p.inv_sb + set * scset;
 }
 
-// Right-looking blocked LU with look-ahead.  Per block step k the trailing
-// update is split into the diagonal block k+1, the rest of block column and
-// row k+1 (the "cross" part) and the rest.  The chain that sets the pace in
-// the late steps -- update of diagonal block k+1, its LU, the strip TRSMs of
-// step k+1, the next diagonal block -- runs back to back on the side stream;
-// the caller's stream performs the cross part and the rest of the update.
-// Each stream waits on the other through one event per hand-over, and in the
-// late steps each such event has fired before the wait is reached.  Two
-// operand sets alternate between consecutive steps; a set is rewritten by
-// the TRSMs of step k+2 only after the side stream has seen the update of
-// step k complete.
+// The trailing updates of the block steps, taken in pairs: block column and
+// row k+1 receive the update of step k alone (they form panel k+1), and
+// everything beyond them the updates of steps k and k+1 in one pass with K =
+// 2 nb (one rounding to the storage format instead of two, half the C
+// traffic).  With steps (k, k+1) a pair (k even in blocks), every element is
+// computed by the same arithmetic however the updates are cut into launches.
+//
+// The operands of step j sit in set (j / nb) & 3 (four sets: two pairs in
+// flight); row r of a set belongs to global row (column) j + nb + r.
+template <int ST, int OP>
+static GemmCall pair_call(const FactorPlan& p, int64_t j, bool pair, int64_t r0, int64_t c0, int64_t M,
+                          int64_t N) {
+    typedef typename Store<ST>::T ST_T;
+    typedef typename Operand<OP>::T OP_T;
+    const int64_t nb = p.nb;
+    const int64_t opset = p.op_rows * nb, scset = p.op_rows / 32;
+    GemmCall g{};
+    g.C = (ST_T*)p.A + r0 + c0 * p.lda;
+    g.ldc = p.lda;
+    g.M = M;
+    g.N = N;
+    auto seg = [&](int64_t step, const void*& a, const void*& b, const float*& sa, const float*& sb) {
+        const int set = (int)((step / nb) & 3);
+        const int64_t ro = r0 - step - nb, co = c0 - step - nb;
+        a = (const OP_T*)p.Lq + set * opset + ro * nb;
+        b = (const OP_T*)p.Uq + set * opset + co * nb;
+        sa = p.inv_sa + set * scset + ro / 32;
+        sb = p.inv_sb + set * scset + co / 32;
+    };
+    g.K = (int)nb;
+    seg(j, g.Aq, g.Bq, g.inv_sa, g.inv_sb);
+    if (pair) {
+        g.K2 = (int)nb;
+        seg(j + nb, g.Aq2, g.Bq2, g.inv_sa2, g.inv_sb2);
+    }
+    return g;
+}
+
+// the update of block column and row b (width w, from global index b) by
+// step j alone or by the pair (j, j+nb): two descriptors
+template <int ST, int OP>
+static int cross_calls(const FactorPlan& p, int64_t j, bool pair, int64_t b, GemmCall* out) {
+    const int64_t n = p.n, w = n - b < p.nb ? n - b : p.nb;
+    int c = 0;
+    out[c++] = pair_call<ST, OP>(p, j, pair, b, b, n - b, w);               // block column b, diagonal included
+    if (n - b - w > 0) out[c++] = pair_call<ST, OP>(p, j, pair, b, b + w, w, n - b - w);   // rest of block row b
+    return c;
+}
+
+// Right-looking blocked LU with look-ahead, the updates taken in pairs (see
+// above).  With the pair (k, k1), k1 = k + nb, and k2, k3 the next two
+// blocks, the caller's stream runs the pair's update in three parts -- the
+// rest of block column and row k2 (the diagonal block k2 is updated on the
+// side stream), block column and row k3, everything beyond -- while the side
+// stream runs the chain that sets the pace of the late steps: the diagonal
+// block k2, its LU, the strip TRSMs of step k2 (after the first part), the
+// update of block column and row k3 by step k2 alone (after the second), the
+// LU and TRSMs of block k3.  One event per hand-over; in the late steps each
+// has fired before its wait is reached.  The operand sets of the pair are
+// rewritten by the TRSMs two pairs later, which the side stream enqueues
+// after it has seen the pair's last update end.
 template <int ST, int OP>
 static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la) {
     typedef typename Store<ST>::T ST_T;
@@ -619,8 +671,6 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     ST_T* A = (ST_T*)p.A;
     const int64_t n = p.n, lda = p.lda;
     const int nb = (int)p.nb;
-    const int64_t opset = p.op_rows * nb;            // elements of one operand buffer
-    const int64_t scset = p.op_rows / 32;             // entries of one scale array
 
     // diagonal-block LU of block k (latency-bound: a handful of small grids)
     auto diag = [&](int64_t k, hipStream_t st) -> hipError_t {
@@ -651,28 +701,30 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
                   4.0 * m * (double)nb * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
         return hipGetLastError();
     };
-    // one trailing-update launch: C[0:M, 0:N] (offset c0 rows, c1 columns
-    // into A22) -= L21[c0:c0+M] U12[c1:c1+N]^T, each launch timed on its own
-    auto gemm = [&](int64_t k, int64_t c0, int64_t c1, int64_t M, int64_t N, hipStream_t st) -> hipError_t {
-        const int set = (int)((k / nb) & 1);
-        const OP_T* Lq = (const OP_T*)p.Lq + set * opset;
-        const OP_T* Uq = (const OP_T*)p.Uq + set * opset;
-        const float* sa = p.inv_sa + set * scset;
-        const float* sb = p.inv_sb + set * scset;
-        ST_T* C = A + (k + nb + c0) + (k + nb + c1) * lda;
+    // one trailing-update launch of up to two descriptors, timed on its own
+    auto gemm = [&](const GemmCall* c, int cnt, hipStream_t st) -> hipError_t {
+        double fl = 0, by = 0;
+        for (int i = 0; i < cnt; ++i) {
+            const double K = c[i].K + c[i].K2;
+            fl += 2.0 * c[i].M * (double)c[i].N * K;
+            by += 2.0 * c[i].M * (double)c[i].N * sizeof(ST_T) + (c[i].M + c[i].N) * K * sizeof(OP_T);
+        }
+        if (fl == 0) return hipSuccess;
         hipEvent_t pt = prof::begin(prof::GEMM, st);
-        hipError_t e2 = gemm_update(OP, ST, C, lda, M, N, nb, Lq + c0 * nb, Uq + c1 * nb, sa + c0 / 32, sb + c1 / 32,
-                                    st, p.gemm_tile);
-        prof::end(pt, prof::GEMM, st, 2.0 * M * (double)N * nb,
-                  2.0 * M * (double)N * sizeof(ST_T) + (M + N) * (double)nb * sizeof(OP_T));
+        hipError_t e2 = gemm_group(OP, ST, p.gemm_tile, c, cnt, st);
+        prof::end(pt, prof::GEMM, st, fl, by);
         return e2;
     };
-    // part: 0 = the whole trailing matrix, 2 = all but block column and row k+1
-    auto update = [&](int64_t k, int part, hipStream_t st) -> hipError_t {
-        const int64_t m = n - k - nb;
-        const int64_t c = nb;                       // width of block column / row k+1
-        if (part == 0) return gemm(k, 0, 0, m, m, st);
-        return gemm(k, c, c, m - c, m - c, st);
+    // block column and row b by step j (pair: by steps j and j + nb)
+    auto cross = [&](int64_t j, bool pair, int64_t b, hipStream_t st) -> hipError_t {
+        GemmCall c[2];
+        const int cnt = cross_calls<ST, OP>(p, j, pair, b, c);
+        return gemm(c, cnt, st);
+    };
+    // the square [b, n) x [b, n) by the pair (j, j + nb)
+    auto square = [&](int64_t j, int64_t b, int64_t w, hipStream_t st) -> hipError_t {
+        GemmCall c = pair_call<ST, OP>(p, j, true, b, b, w, w);
+        return gemm(&c, 1, st);
     };
 
     if ((e = fill_u64(p.info, 1, ~0ull, s))) return e;
@@ -680,39 +732,52 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         const int64_t words = ((n + nb - 1) / nb) * (int64_t)diag_sync_words();
         if ((e = fill_u64(p.dsync, (words + 1) / 2, 0ull, s))) return e;
     }
+    // panels 0 and 1 (block column and row 1 updated by step 0 alone)
     if ((e = diag(0, s))) return e;
     if ((e = trsm(0, s))) return e;
-    // side stream: panel 0 and the untouched trailing matrix are ready
+    if (nb < n) {
+        if ((e = cross(0, false, nb, s))) return e;
+        if ((e = diag(nb, s))) return e;
+        if ((e = trsm(nb, s))) return e;
+    }
     if ((e = hipEventRecord(LA->ev_upd, s))) return e;
     bool side_used = false;
-    for (int64_t k = 0; k + nb < n; k += nb) {
-        const int64_t m = n - k - nb;               // trailing size after step k
-        if (m > nb) {
-            const int64_t c = nb;
-            // side: diagonal block k+1 (needs the update of step k-1 and panel k), its LU
-            if ((e = hipStreamWaitEvent(LA->side, LA->ev_upd, 0))) return e;
-            if ((e = gemm(k, 0, 0, c, c, LA->side))) return e;
-            if ((e = diag(k + nb, LA->side))) return e;
-            // main: the rest of block column and row k+1 (needs panel k)
-            if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
-            if ((e = gemm(k, c, 0, m - c, c, s))) return e;
-            if ((e = gemm(k, 0, c, c, m - c, s))) return e;
-            if ((e = hipEventRecord(LA->ev_cross, s))) return e;
-            // side: panel k+1
-            if ((e = hipStreamWaitEvent(LA->side, LA->ev_cross, 0))) return e;
-            if ((e = trsm(k + nb, LA->side))) return e;
-            if ((e = hipEventRecord(LA->ev_panel, LA->side))) return e;
-            side_used = true;
-            // main: the rest of the update of step k
-            if ((e = update(k, 2, s))) return e;
-            if ((e = hipEventRecord(LA->ev_upd, s))) return e;
-        } else {
-            if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
-            side_used = false;
-            if ((e = update(k, 0, s))) return e;
-            if ((e = diag(k + nb, s))) return e;
-            if ((e = trsm(k + nb, s))) return e;
+    for (int64_t k = 0; k + 2 * nb < n; k += 2 * nb) {
+        // panels k and k1 = k + nb are formed; the pair (k, k1) updates [k2, n)
+        const int64_t k2 = k + 2 * nb, k3 = k2 + nb;
+        const int64_t w2 = n - k2 < nb ? n - k2 : nb;
+        // side: diagonal block k2 (needs the previous pair's last update), its LU
+        if ((e = hipStreamWaitEvent(LA->side, LA->ev_upd, 0))) return e;
+        if ((e = square(k, k2, w2, LA->side))) return e;
+        if ((e = diag(k2, LA->side))) return e;
+        // main: the rest of block column and row k2 (needs panel k1)
+        if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
+        if (n - k2 - w2 > 0) {
+            GemmCall c[2] = {pair_call<ST, OP>(p, k, true, k2 + w2, k2, n - k2 - w2, w2),
+                             pair_call<ST, OP>(p, k, true, k2, k2 + w2, w2, n - k2 - w2)};
+            if ((e = gemm(c, 2, s))) return e;
         }
+        if ((e = hipEventRecord(LA->ev_cross, s))) return e;
+        if (k3 < n) {
+            const int64_t w3 = n - k3 < nb ? n - k3 : nb;
+            // main: block column and row k3, then everything beyond
+            if ((e = cross(k, true, k3, s))) return e;
+            if ((e = hipEventRecord(LA->ev_next, s))) return e;
+            if (n - k3 - w3 > 0) {
+                GemmCall c = pair_call<ST, OP>(p, k, true, k3 + w3, k3 + w3, n - k3 - w3, n - k3 - w3);
+                if ((e = gemm(&c, 1, s))) return e;
+            }
+            if ((e = hipEventRecord(LA->ev_upd, s))) return e;
+            // side: panel k2, block column and row k3 by step k2, panel k3
+            if ((e = hipStreamWaitEvent(LA->side, LA->ev_cross, 0))) return e;
+            if ((e = trsm(k2, LA->side))) return e;
+            if ((e = hipStreamWaitEvent(LA->side, LA->ev_next, 0))) return e;
+            if ((e = cross(k2, false, k3, LA->side))) return e;
+            if ((e = diag(k3, LA->side))) return e;
+            if ((e = trsm(k3, LA->side))) return e;
+        }
+        if ((e = hipEventRecord(LA->ev_panel, LA->side))) return e;
+        side_used = true;
     }
     // the caller's stream ends after every side-stream kernel
     if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
@@ -743,6 +808,7 @@ static hipError_t factor_dispatch(const FactorPlan& p, hipStream_t s, Lookahead*
 
 template <int ST, int OP>
 static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t s) {
+    typedef typename Store<ST>::T ST_T;
     typedef typename Operand<OP>::T OP_T;
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void*)k_trsm<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -763,11 +829,11 @@ static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t
         if ((e = fill_u64(p.dsync, (words + 1) / 2, 0ull, s))) return e;
         steps = nblk > steps ? nblk : steps;
     }
-    for (int64_t t = 0; t < steps; ++t) {
+    // panel t (diagonal-block LU, strip TRSMs) of every factorisation that has block t
+    auto panels = [&](int64_t t) -> hipError_t {
         DiagCall dc[GEMM_GROUP_MAX];
         TrsmGroup tg;
-        GemmCall gc[GEMM_GROUP_MAX];
-        int nd = 0, nt = 0, ng = 0, wg = 0, nbmax = 64;
+        int nd = 0, nt = 0, wg = 0, nbmax = 64;
         for (int g = 0; g < count; ++g) {
             const FactorPlan& p = P[g];
             const int nb = (int)p.nb;
@@ -782,29 +848,50 @@ static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t
             trsm_desc<ST, OP>(p, k, tg.g[nt], wg);
             wg = tg.g[nt++].wg_end;
             nbmax = nb > nbmax ? nb : nbmax;
-            const int set = (int)(blk & 1);
-            const int64_t opset = p.op_rows * nb, scset = p.op_rows / 32;
-            gc[ng++] = GemmCall{(typename Store<ST>::T*)p.A + (k + nb) + (k + nb) * p.lda, p.lda, m, m, nb,
-                                (const OP_T*)p.Lq + set * opset, (const OP_T*)p.Uq + set * opset,
-                                p.inv_sa + set * scset, p.inv_sb + set * scset};
         }
-        if ((e = diag_lu_group(ST, dc, nd, s))) return e;
-        if (nt) {
-            tg.count = nt;
-            hipEvent_t pt = prof::begin(prof::TRSM, s);
-            k_trsm<ST, OP><<<wg, 256, trsm_smem(nbmax), s>>>(tg);
-            prof::end(pt, prof::TRSM, s, 0.0, 0.0);
-            if ((e = hipGetLastError())) return e;
-            hipEvent_t pg = prof::begin(prof::GEMM, s);
-            if ((e = gemm_group(OP, ST, P[0].gemm_tile, gc, ng, s))) return e;
-            double fl = 0, by = 0;
-            for (int i = 0; i < ng; ++i) {
-                fl += 2.0 * gc[i].M * (double)gc[i].N * gc[i].K;
-                by += 2.0 * gc[i].M * (double)gc[i].N * sizeof(typename Store<ST>::T) +
-                      (gc[i].M + gc[i].N) * (double)gc[i].K * sizeof(OP_T);
-            }
-            prof::end(pg, prof::GEMM, s, fl, by);
+        if (!nd) return hipSuccess;
+        hipError_t e2 = diag_lu_group(ST, dc, nd, s);
+        if (e2 || !nt) return e2;
+        tg.count = nt;
+        hipEvent_t pt = prof::begin(prof::TRSM, s);
+        k_trsm<ST, OP><<<wg, 256, trsm_smem(nbmax), s>>>(tg);
+        prof::end(pt, prof::TRSM, s, 0.0, 0.0);
+        return hipGetLastError();
+    };
+    auto gemms = [&](const GemmCall* gc, int ng) -> hipError_t {
+        if (!ng) return hipSuccess;
+        double fl = 0, by = 0;
+        for (int i = 0; i < ng; ++i) {
+            const double K = gc[i].K + gc[i].K2;
+            fl += 2.0 * gc[i].M * (double)gc[i].N * K;
+            by += 2.0 * gc[i].M * (double)gc[i].N * sizeof(ST_T) + (gc[i].M + gc[i].N) * K * sizeof(OP_T);
         }
+        hipEvent_t pg = prof::begin(prof::GEMM, s);
+        hipError_t e2 = gemm_group(OP, ST, P[0].gemm_tile, gc, ng, s);
+        prof::end(pg, prof::GEMM, s, fl, by);
+        return e2;
+    };
+    // the updates in pairs of steps, with the arithmetic of mxp_factor:
+    // panel t, block column and row t+1 by step t alone, panel t+1, the rest
+    // by steps t and t+1 in one pass
+    for (int64_t t = 0; t < steps; t += 2) {
+        if ((e = panels(t))) return e;
+        GemmCall gc[GEMM_DESC_MAX];
+        int ng = 0;
+        for (int g = 0; g < count; ++g) {
+            const FactorPlan& p = P[g];
+            const int64_t b = (t + 1) * p.nb;
+            if (b < p.n) ng += cross_calls<ST, OP>(p, t * p.nb, false, b, gc + ng);
+        }
+        if ((e = gemms(gc, ng))) return e;
+        if ((e = panels(t + 1))) return e;
+        ng = 0;
+        for (int g = 0; g < count; ++g) {
+            const FactorPlan& p = P[g];
+            const int64_t b = (t + 2) * p.nb;
+            if (b < p.n) gc[ng++] = pair_call<ST, OP>(p, t * p.nb, true, b, b, p.n - b, p.n - b);
+        }
+        if ((e = gemms(gc, ng))) return e;
     }
     for (int g = 0; g < count; ++g) {
         const FactorPlan& p = P[g];

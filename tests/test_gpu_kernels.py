@@ -54,10 +54,22 @@ def test_trailing_update_full_tiles_aligned(M, N, K, update, store):
     _run_update(M, N, K, update, store, aligned=True)
 
 
-def _run_update(M, N, K, update, store, aligned):
-    print("gemm", M, N, K, update, store, "aligned" if aligned else "", flush=True)
-    g = torch.Generator().manual_seed(M * 7 + N)
-    Mp, Np = _pad(M, 256), _pad(N, 256)
+# two block steps in one pass (mxp_trailing_update2): the second segment
+# with other scale factors, some rows and columns with both
+@pytest.mark.parametrize("M,N,K1,K2,update,store,aligned", [
+    (1024, 1024, 512, 512, "f16", "f16", True),
+    (1000, 900, 512, 512, "bf16", "bf16", True),
+    (768, 1024, 256, 256, "f8", "f16", True),
+    (1300, 517, 128, 128, "f8", "bf16", True),
+    (300, 520, 512, 512, "f16", "f16", False),
+    (200, 333, 64, 64, "f32", "f32", False),
+    (384, 129, 128, 256, "f16", "f32", False),
+])
+def test_two_step_update_matches_definition(M, N, K1, K2, update, store, aligned):
+    _run_update(M, N, K1, update, store, aligned=aligned, K2=K2)
+
+
+def _operands(g, Mp, Np, K, update):
     A = torch.rand((Mp, K), generator=g, dtype=torch.float64) * 2 - 1
     B = torch.rand((Np, K), generator=g, dtype=torch.float64) * 2 - 1
     scale_op = 200.0 if update == "f8" else 1.0
@@ -65,23 +77,40 @@ def _run_update(M, N, K, update, store, aligned):
     Bq = (B.float() * scale_op).to(TORCH_OP[update])
     ia = torch.pow(2.0, torch.randint(-20, -5, (Mp // 32,), generator=g).double()).float()
     ib = torch.pow(2.0, torch.randint(-8, 3, (Np // 32,), generator=g).double()).float()
+    return Aq, Bq, ia, ib
+
+
+def _run_update(M, N, K, update, store, aligned, K2=0):
+    print("gemm", M, N, K, K2, update, store, "aligned" if aligned else "", flush=True)
+    g = torch.Generator().manual_seed(M * 7 + N + K2)
+    Mp, Np = _pad(M, 256), _pad(N, 256)
+    segs = [_operands(g, Mp, Np, K, update)] + ([_operands(g, Mp, Np, K2, update)] if K2 else [])
     if aligned:
         ldc = _pad(M, 8) + 64
     else:
         ldc = M + 3 if store != "f32" else M + 4
     C = (torch.rand((N, ldc), generator=g, dtype=torch.float64) * 8 - 4).to(TORCH_ST[store])
     Cd = C.cuda()
-    mxp.mxp_trailing_update(Cd, ldc, M, N, K, update, store, Aq.cuda(), Bq.cuda(), ia.cuda(), ib.cuda())
+    if K2:
+        (A1, B1, a1, b1), (A2, B2, a2, b2) = segs
+        mxp.mxp_trailing_update2(Cd, ldc, M, N, K, K2, update, store, A1.cuda(), B1.cuda(), a1.cuda(), b1.cuda(),
+                                 A2.cuda(), B2.cuda(), a2.cuda(), b2.cuda())
+    else:
+        Aq, Bq, ia, ib = segs[0]
+        mxp.mxp_trailing_update(Cd, ldc, M, N, K, update, store, Aq.cuda(), Bq.cuda(), ia.cuda(), ib.cuda())
     got = Cd.cpu().double()
-    a = Aq.double()[:M].numpy()
-    b = Bq.double()[:N].numpy()
-    da = np.repeat(ia.double().numpy(), 32)[:M]
-    db = np.repeat(ib.double().numpy(), 32)[:N]
     C0 = C.double().numpy()[:, :M].T           # M x N
-    prod = (a @ b.T) * da[:, None] * db[None, :]
+    prod = np.zeros((M, N))
+    mag = np.abs(C0)
+    for Aq, Bq, ia, ib in segs:
+        a = Aq.double()[:M].numpy()
+        b = Bq.double()[:N].numpy()
+        da = np.repeat(ia.double().numpy(), 32)[:M]
+        db = np.repeat(ib.double().numpy(), 32)[:N]
+        prod += (a @ b.T) * da[:, None] * db[None, :]
+        mag = mag + (np.abs(a) @ np.abs(b).T) * da[:, None] * db[None, :]
     ref = C0 - prod
-    mag = np.abs(C0) + (np.abs(a) @ np.abs(b).T) * da[:, None] * db[None, :]
-    bound = U_ST[store] * np.abs(ref) + SUB_ST[store] + (K + 2) * 2.0 ** -24 * mag
+    bound = U_ST[store] * np.abs(ref) + SUB_ST[store] + (K + K2 + 2) * 2.0 ** -24 * mag
     err = np.abs(got.numpy()[:, :M].T - ref)
     assert np.all(err <= bound), float((err / bound).max())
     # padding rows of C (ld > M) untouched
