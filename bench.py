@@ -206,6 +206,13 @@ def summarize_stats(args):
             f.write("%-60s %7d %12.3f %12.2f %7.2f\n" % (name, int(r["Calls"]), float(r["TotalDurationNs"]) / 1e6,
                                                         float(r["AverageNs"]) / 1e3,
                                                         100.0 * float(r["TotalDurationNs"]) / total))
+        # the trailing update over both work-group tiles (what bench.py's roofline averages over)
+        upd = [r for r in rows if "k_gemm_update<" in r["Name"]]
+        if len(upd) > 1:
+            calls = sum(int(r["Calls"]) for r in upd)
+            tns = sum(float(r["TotalDurationNs"]) for r in upd)
+            f.write("%-60s %7d %12.3f %12.2f %7.2f\n" % ("k_gemm_update, all tiles", calls, tns / 1e6,
+                                                        tns / calls / 1e3, 100.0 * tns / total))
     print(open(fn).read())
 
 

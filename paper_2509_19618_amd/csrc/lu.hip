@@ -710,8 +710,15 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
             by += 2.0 * c[i].M * (double)c[i].N * sizeof(ST_T) + (c[i].M + c[i].N) * K * sizeof(OP_T);
         }
         if (fl == 0) return hipSuccess;
+        // launches of fewer 256-row tiles than CUs (the late steps, the
+        // diagonal block) take 128-row tiles: twice the work-groups, the
+        // same arithmetic per element
+        int tile = p.gemm_tile;
+        int64_t tiles = 0;
+        for (int i = 0; i < cnt; ++i) tiles += ((c[i].M + 255) / 256) * ((c[i].N + 127) / 128);
+        if (tiles < 256) tile = GEMM_TILE_128;
         hipEvent_t pt = prof::begin(prof::GEMM, st);
-        hipError_t e2 = gemm_group(OP, ST, p.gemm_tile, c, cnt, st);
+        hipError_t e2 = gemm_group(OP, ST, tile, c, cnt, st);
         prof::end(pt, prof::GEMM, st, fl, by);
         return e2;
     };
