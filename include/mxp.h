@@ -202,13 +202,18 @@ int mxp_factor_group(int count, const mxp_factor_item *items, int update, int st
  *                   stored 32-row strip of L21 (entry [blk][r/32]; the
  *                   stored value is s * L), 1 where no scaling is applied
  *         rowscale  FP64 n: the row scaling S (1 without equilibration)
- *         linv_full/uinv_full FP32 nblk x nb x nb: L11^-1 and U11^-1
+ *         linv_full/uinv_full FP32 ngrp x D x D, column-major (ld D): the
+ *                   inverses of the unit-lower and upper parts of the
+ *                   preconditioner's diagonal blocks -- pairs of factor
+ *                   blocks (D = 2 nb) for nb <= 512, single ones (D = nb)
+ *                   otherwise; ngrp = ceil(n / D)
  *   work: Lq/Uq     four sets of op_rows x nb update operands
  *                   (row-major: K contiguous), set (k/nb) & 3 for step k;
  *                   row 0 of a set is the first row after the step's block
  *         inv_sa/inv_sb four sets of op_rows/32 FP32 factors 1/s per
  *                   32-row strip of Lq / Uq
  *         info      unsigned 64-bit: first failing pivot column, ~0 if none
+ *         (then scratch of the preconditioner's inverses)
  * Returns MXP_EINVAL for sizes mxp_factor would reject.
  */
 typedef struct {

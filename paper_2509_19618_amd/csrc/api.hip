@@ -113,11 +113,13 @@ static FactorPlan make_plan(int64_t n, int64_t nb, int update, int store, void* 
         p.inv_sb = (float*)(w + wl.inv_sb);
         p.info = (unsigned long long*)(w + wl.info);
         p.dsync = (int*)(w + wl.dsync);
+        p.pairw = (float*)(w + wl.pairw);
     } else {
         p.Lq = p.Uq = nullptr;
         p.inv_sa = p.inv_sb = nullptr;
         p.info = nullptr;
         p.dsync = nullptr;
+        p.pairw = nullptr;
     }
     return p;
 }

@@ -113,6 +113,10 @@ constexpr int NBUF = 3;            // stages in LDS: two copies in flight while 
 constexpr int GCH = GBK / 16;      // 16-byte chunks per operand row
 constexpr int SB = TN * GBK;       // bytes of one B stage
 constexpr int GGROUP = 8;          // tile rows per group in the tile order
+#ifndef MXP_GGROUP2
+#define MXP_GGROUP2 4
+#endif
+constexpr int GGROUP2 = MXP_GGROUP2;   // the same for two-segment updates (twice the operand bytes per tile row)
 
 // Direct global->LDS copy of 16 bytes per lane: lane L lands at l + 16 L
 // (l is wave-uniform).  gfx950 global_load_lds_dwordx4.
@@ -245,9 +249,10 @@ __global__ __launch_bounds__(256, 2) void k_gemm_update(const GemmGroup grp) {
     const float* __restrict__ inv_sa = G.K2 ? G.inv_sa2 : G.inv_sa;
     const float* __restrict__ inv_sb = G.K2 ? G.inv_sb2 : G.inv_sb;
     const int lin = glin - (d > 0 ? grp.g[d - 1].tile_end : 0);
-    const int group_size = GGROUP * tiles_n;
-    const int first_m = (lin / group_size) * GGROUP;
-    const int gm = (tiles_m - first_m) < GGROUP ? (tiles_m - first_m) : GGROUP;
+    const int gg = G.K2 ? GGROUP2 : GGROUP;
+    const int group_size = gg * tiles_n;
+    const int first_m = (lin / group_size) * gg;
+    const int gm = (tiles_m - first_m) < gg ? (tiles_m - first_m) : gg;
     const int tm = first_m + (lin % group_size) % gm;
     const int tn = (lin % group_size) / gm;
     const int64_t row0 = (int64_t)tm * TMv, col0 = (int64_t)tn * TN;

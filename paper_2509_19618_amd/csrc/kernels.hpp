@@ -40,14 +40,16 @@ struct FactorPlan {
     float* uinv;     // same for U
     float* lsc;      // nblk x ceil(n/32): power-of-two scale of every stored 32-row strip of L21
     double* rowscale;  // n
-    float* linv_full;  // nblk x nb x nb: L11^-1 of every diagonal block (FP32, ld nb)
-    float* uinv_full;  // nblk x nb x nb: U11^-1
+    float* linv_full;  // ngrp x D x D (D = prec_block(nb)): inverses of the unit-lower parts of the
+                       // preconditioner's diagonal blocks (FP32, column-major, ld D)
+    float* uinv_full;  // the same for the upper parts
     // work (scratch)
     int64_t op_rows; // rows of one operand set (operand_rows(n))
-    void* Lq;        // 2 sets of op_rows x nb operands (K-major)
-    void* Uq;        // 2 sets of op_rows x nb operands (K-major)
-    float* inv_sa;   // 2 sets of op_rows/32
-    float* inv_sb;   // 2 sets of op_rows/32
+    void* Lq;        // 4 sets of op_rows x nb operands (K-major)
+    void* Uq;        // 4 sets of op_rows x nb operands (K-major)
+    float* inv_sa;   // 4 sets of op_rows/32
+    float* inv_sb;   // 4 sets of op_rows/32
+    float* pairw;    // ceil(n / 2nb) x nb x nb: scratch of the pair inverses (D = 2 nb only)
     unsigned long long* info;  // 1
     int* dsync;      // nblk x diag_sync_words(): phase counters of the diagonal-block LUs (zeroed per factorisation)
     int gemm_tile = 0;  // work-group tile of the trailing update (GEMM_TILE_*)
@@ -57,9 +59,13 @@ struct AuxLayout {
     size_t T, Trm, linv, uinv, lsc, rowscale, linv_full, uinv_full, total;
 };
 struct WorkLayout {
-    size_t Lq, Uq, inv_sa, inv_sb, info, dsync, total;
+    size_t Lq, Uq, inv_sa, inv_sb, info, dsync, pairw, total;
 };
 AuxLayout aux_layout(int64_t n, int64_t nb);
+// diagonal-block size of the preconditioner's substitution: pairs of factor
+// blocks for nb <= 512 (one hand-over between work-groups per pair), the
+// factor blocks otherwise
+__host__ __device__ inline int64_t prec_block(int64_t nb) { return nb <= 512 ? 2 * nb : nb; }
 int64_t operand_rows(int64_t n);
 WorkLayout work_layout(int64_t n, int64_t nb, int update);
 int dtype_bytes(int dt);

@@ -45,8 +45,9 @@ AuxLayout aux_layout(int64_t n, int64_t nb) {
     L.uinv = off; off = al256(off + (size_t)nblk * nb * 64 * 4);
     L.lsc = off; off = al256(off + (size_t)nblk * ((n + 31) / 32) * 4);
     L.rowscale = off; off = al256(off + (size_t)n * 8);
-    L.linv_full = off; off = al256(off + (size_t)nblk * nb * nb * 4);
-    L.uinv_full = off; off = al256(off + (size_t)nblk * nb * nb * 4);
+    const int64_t D = prec_block(nb), ngrp = (n + D - 1) / D;
+    L.linv_full = off; off = al256(off + (size_t)ngrp * D * D * 4);
+    L.uinv_full = off; off = al256(off + (size_t)ngrp * D * D * 4);
     L.total = off;
     return L;
 }
@@ -66,6 +67,8 @@ WorkLayout work_layout(int64_t n, int64_t nb, int update) {
     W.inv_sb = off; off = al256(off + 4 * (size_t)(rows / 32) * 4);
     W.info = off; off = al256(off + 8);
     W.dsync = off; off = al256(off + (size_t)((n + nb - 1) / nb) * diag_sync_words() * 4);
+    W.pairw = off;
+    if (prec_block(nb) == 2 * nb) off = al256(off + (size_t)((n + 2 * nb - 1) / (2 * nb)) * nb * nb * 4);
     W.total = off;
     return W;
 }
@@ -478,10 +481,12 @@ __global__ __launch_bounds__(256) void k_inv_upper(int64_t n, int nb, const floa
     }
     __syncthreads();
     strip_right_solve(S, SP, kbp / 64, Trm_all + blk * nb * nb, nb, uinv_all + blk * nb * 64, red);
-    float* out = out_all + blk * nb * nb;
+    // block blk is diagonal block blk % g of group blk / g (column-major, ld D)
+    const int64_t D = prec_block(nb), g = D / nb, o = (blk % g) * nb;
+    float* out = out_all + (blk / g) * D * D + o + o * D;
     for (int e = threadIdx.x; e < SR * kbp; e += 256) {
         int ii = e % SR, c = e / SR;
-        out[(r0 + ii) + (int64_t)c * nb] = S[ii * SP + c];
+        out[(r0 + ii) + (int64_t)c * D] = S[ii * SP + c];
     }
 }
 
@@ -503,11 +508,150 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
     }
     __syncthreads();
     strip_left_solve(S, SP, kbp / 64, Tall + blk * nb * nb, nb, linv_all + blk * nb * 64, red);
-    float* out = out_all + blk * nb * nb;
+    const int64_t D = prec_block(nb), g = D / nb, o = (blk % g) * nb;
+    float* out = out_all + (blk / g) * D * D + o + o * D;
     for (int e = threadIdx.x; e < SR * kbp; e += 256) {
         int kk = e % kbp, cc = e / kbp;
-        out[kk + (int64_t)(c0 + cc) * nb] = S[cc * SP + kk];
+        out[kk + (int64_t)(c0 + cc) * D] = S[cc * SP + kk];
     }
+}
+
+// Off-diagonal blocks of the inverses of the pairs of diagonal blocks
+// (blocks b0 = 2p, b1 = 2p + 1 of sizes nb and kb1):
+//   [[L0, 0], [B, L1]]^-1 = [[L0^-1, 0], [-L1^-1 B L0^-1, L1^-1]],
+//   [[U0, B'], [0, U1]]^-1 = [[U0^-1, -U0^-1 B' U1^-1], [0, U1^-1]],
+// with B and B' the stored panels of the factor (B with its strip factors
+// undone) and the diagonal inverses from k_inv_lower / k_inv_upper.  Each
+// product is one launch over all pairs (blockIdx.z = pair) of 64 x 64
+// output tiles on the FP32 matrix cores; the K range of a tile skips the
+// zero triangle of its triangular operand.
+constexpr int PP_SP = 96;   // LDS pitch of a staged 32 x 64 operand (two k rows fall in distinct banks)
+
+// acc (wave (wr, wc)'s 32 x 32 part of the 64 x 64 tile) += A[i0.., k] B[k, j0..] over k in [k_lo, k_hi)
+template <class FA, class FB>
+MXP_DEV f16v_t pair_tile(FA fa, FB fb, int M, int N, int i0, int j0, int k_lo, int k_hi, float* sA, float* sB) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = wave & 1, wc = wave >> 1, lr = lane & 31, lh = lane >> 5;
+    f16v_t acc = {};
+    for (int k0 = k_lo; k0 < k_hi; k0 += 32) {
+        for (int e = tid; e < 2048; e += 256) {
+            const int r = e & 63, kk = e >> 6;            // A: rows contiguous
+            const int i = i0 + r, k = k0 + kk;
+            sA[kk * PP_SP + r] = (i < M && k < k_hi) ? fa(i, k) : 0.0f;
+            const int kb = e & 31, c = e >> 5;            // B: k contiguous
+            const int kq = k0 + kb, j = j0 + c;
+            sB[kb * PP_SP + c] = (j < N && kq < k_hi) ? fb(kq, j) : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) {
+            const int kk = 2 * s2 + lh;
+            acc = mfma2(sA[kk * PP_SP + wr * 32 + lr], sB[kk * PP_SP + wc * 32 + lr], acc);
+        }
+        __syncthreads();
+    }
+    return acc;
+}
+
+// C[i][j] = alpha acc, register q of lane l holding row 8(q/4) + 4(l/32) + q%4, column l%32
+template <class FC>
+MXP_DEV void pair_store(const f16v_t& acc, float alpha, int M, int N, int i0, int j0, FC fc) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wr = wave & 1, wc = wave >> 1;
+    const int j = j0 + wc * 32 + (lane & 31);
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int i = i0 + wr * 32 + 8 * (q >> 2) + 4 * (lane >> 5) + (q & 3);
+        if (i < M && j < N) fc(i, j, alpha * acc[q]);
+    }
+}
+
+// phase 0: W = B L0^-1 (kb1 x nb, ld nb, into W), phase 1: X = -L1^-1 W
+template <int ST>
+__global__ __launch_bounds__(256) void k_pair_lower(int64_t n, int nb, const typename Store<ST>::T* __restrict__ A,
+                                                    int64_t lda, const float* __restrict__ lsc, int64_t nstrips32,
+                                                    float* __restrict__ inv_all, float* __restrict__ W, int phase) {
+    __shared__ float sA[32 * PP_SP], sB[32 * PP_SP];
+    const int64_t p = blockIdx.z, D = 2 * (int64_t)nb;
+    const int64_t k0 = p * D, k1 = k0 + nb;
+    if (k1 >= n) return;
+    const int kb1 = (int)(n - k1 < nb ? n - k1 : nb);
+    float* inv = inv_all + p * D * D;
+    float* Wp = W + p * (int64_t)nb * nb;
+    const int i0 = 64 * blockIdx.y, j0 = 64 * blockIdx.x;
+    if (phase == 0) {
+        if (i0 >= kb1) return;
+        const float* srow = lsc + (2 * p) * nstrips32;
+        auto fa = [&](int i, int k) {
+            return Store<ST>::load(A, (k1 + i) + (k0 + k) * lda) / srow[(k1 + i) / 32];
+        };
+        auto fb = [&](int k, int j) { return inv[k + (int64_t)j * D]; };
+        const f16v_t acc = pair_tile(fa, fb, kb1, nb, i0, j0, j0, nb, sA, sB);   // L0^-1[k][j] = 0 for k < j
+        pair_store(acc, 1.0f, kb1, nb, i0, j0, [&](int i, int j, float v) { Wp[i + (int64_t)j * nb] = v; });
+    } else {
+        if (i0 >= kb1) return;
+        auto fa = [&](int i, int k) { return inv[(nb + i) + (int64_t)(nb + k) * D]; };
+        auto fb = [&](int k, int j) { return Wp[k + (int64_t)j * nb]; };
+        const int kh = i0 + 64 < kb1 ? i0 + 64 : kb1;                             // L1^-1[i][k] = 0 for k > i
+        const f16v_t acc = pair_tile(fa, fb, kb1, nb, i0, j0, 0, kh, sA, sB);
+        pair_store(acc, -1.0f, kb1, nb, i0, j0, [&](int i, int j, float v) { inv[(nb + i) + (int64_t)j * D] = v; });
+    }
+}
+
+// phase 0: W = U0^-1 B' (nb x kb1, ld nb, into W), phase 1: Y = -W U1^-1
+template <int ST>
+__global__ __launch_bounds__(256) void k_pair_upper(int64_t n, int nb, const typename Store<ST>::T* __restrict__ A,
+                                                    int64_t lda, float* __restrict__ inv_all, float* __restrict__ W,
+                                                    int phase) {
+    __shared__ float sA[32 * PP_SP], sB[32 * PP_SP];
+    const int64_t p = blockIdx.z, D = 2 * (int64_t)nb;
+    const int64_t k0 = p * D, k1 = k0 + nb;
+    if (k1 >= n) return;
+    const int kb1 = (int)(n - k1 < nb ? n - k1 : nb);
+    float* inv = inv_all + p * D * D;
+    float* Wp = W + p * (int64_t)nb * nb;
+    const int i0 = 64 * blockIdx.y, j0 = 64 * blockIdx.x;
+    if (j0 >= kb1) return;
+    if (phase == 0) {
+        auto fa = [&](int i, int k) { return inv[i + (int64_t)k * D]; };
+        auto fb = [&](int k, int j) { return Store<ST>::load(A, (k0 + k) + (k1 + j) * lda); };
+        const f16v_t acc = pair_tile(fa, fb, nb, kb1, i0, j0, i0, nb, sA, sB);   // U0^-1[i][k] = 0 for k < i
+        pair_store(acc, 1.0f, nb, kb1, i0, j0, [&](int i, int j, float v) { Wp[i + (int64_t)j * nb] = v; });
+    } else {
+        auto fa = [&](int i, int k) { return Wp[i + (int64_t)k * nb]; };
+        auto fb = [&](int k, int j) { return inv[(nb + k) + (int64_t)(nb + j) * D]; };
+        const int kh = j0 + 64 < kb1 ? j0 + 64 : kb1;                             // U1^-1[k][j] = 0 for k > j
+        const f16v_t acc = pair_tile(fa, fb, nb, kb1, i0, j0, 0, kh, sA, sB);
+        pair_store(acc, -1.0f, nb, kb1, i0, j0, [&](int i, int j, float v) { inv[i + (int64_t)(nb + j) * D] = v; });
+    }
+}
+
+// the full FP32 inverses of the preconditioner's diagonal blocks (after the
+// factorisation): every factor block's, then the off-diagonal blocks of the
+// pairs.  W: scratch of ceil(n / 2nb) nb^2 floats.
+template <int ST>
+static hipError_t prec_inverses(const FactorPlan& p, float* W, hipStream_t s) {
+    const int64_t n = p.n, nb = p.nb;
+    const int64_t nblk = (n + nb - 1) / nb;
+    dim3 g((unsigned)(nb / SR), (unsigned)nblk);
+    hipEvent_t pt = prof::begin(prof::DIAG, s);
+    k_inv_upper<<<g, 256, trsm_smem((int)nb), s>>>(n, (int)nb, p.Trm, p.uinv, p.uinv_full);
+    k_inv_lower<<<g, 256, trsm_smem((int)nb), s>>>(n, (int)nb, p.T, p.linv, p.linv_full);
+    double fl = 2.0 / 3.0 * (double)n * nb * nb;
+    if (prec_block(nb) == 2 * nb && n > nb) {
+        const int64_t npair = (n + 2 * nb - 1) / (2 * nb);
+        const dim3 gp((unsigned)(nb / 64), (unsigned)(nb / 64), (unsigned)npair);
+        typedef typename Store<ST>::T T;
+        // the lower and then the upper products, each pair of launches through W
+        for (int ph = 0; ph < 2; ++ph)
+            k_pair_lower<ST><<<gp, 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, p.lsc, (n + 31) / 32, p.linv_full,
+                                                W, ph);
+        for (int ph = 0; ph < 2; ++ph)
+            k_pair_upper<ST><<<gp, 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, p.uinv_full, W, ph);
+        fl += 4.0 * (double)n * nb * nb;
+    }
+    prof::end(pt, prof::DIAG, s, fl, 16.0 * (double)n * nb);
+    return hipGetLastError();
 }
 
 // ============================================================== driver
@@ -788,17 +932,8 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     }
     // the caller's stream ends after every side-stream kernel
     if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
-    // full FP32 inverses of every diagonal block, used by the preconditioner
-    {
-        const int64_t nblk = (n + nb - 1) / nb;
-        dim3 g((unsigned)(nb / SR), (unsigned)nblk);
-        hipEvent_t pt = prof::begin(prof::DIAG, s);
-        k_inv_upper<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.Trm, p.uinv, p.uinv_full);
-        k_inv_lower<<<g, 256, trsm_smem(nb), s>>>(n, nb, p.T, p.linv, p.linv_full);
-        prof::end(pt, prof::DIAG, s, 2.0 / 3.0 * (double)n * nb * nb, 16.0 * (double)n * nb);
-        if ((e = hipGetLastError())) return e;
-    }
-    return hipSuccess;
+    // full FP32 inverses of the preconditioner's diagonal blocks
+    return prec_inverses<ST>(p, p.pairw, s);
 }
 
 static hipError_t factor_dispatch(const FactorPlan& p, hipStream_t s, Lookahead* la) {
@@ -900,15 +1035,8 @@ static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t
         }
         if ((e = gemms(gc, ng))) return e;
     }
-    for (int g = 0; g < count; ++g) {
-        const FactorPlan& p = P[g];
-        const int nb = (int)p.nb;
-        const int64_t nblk = (p.n + nb - 1) / nb;
-        dim3 gr((unsigned)(nb / SR), (unsigned)nblk);
-        k_inv_upper<<<gr, 256, trsm_smem(nb), s>>>(p.n, nb, p.Trm, p.uinv, p.uinv_full);
-        k_inv_lower<<<gr, 256, trsm_smem(nb), s>>>(p.n, nb, p.T, p.linv, p.linv_full);
-        if ((e = hipGetLastError())) return e;
-    }
+    for (int g = 0; g < count; ++g)
+        if ((e = prec_inverses<ST>(P[g], P[g].pairw, s))) return e;
     return hipSuccess;
 }
 

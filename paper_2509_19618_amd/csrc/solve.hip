@@ -106,7 +106,7 @@ __device__ void signal_flag(unsigned* flag) {
 }
 
 template <int ST, bool LOWER>
-__global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename Store<ST>::T* __restrict__ A,
+__global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const typename Store<ST>::T* __restrict__ A,
                                               int64_t lda, int vec, const float* __restrict__ inv_all,
                                               const float* __restrict__ lsc, int64_t nstrips32,
                                               const double* __restrict__ rhs, int64_t ld_rhs,
@@ -127,22 +127,26 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
     out += blockIdx.y * ld_out;
     tbuf += blockIdx.y * n;
     flags += blockIdx.y * flag_stride;
-    const int64_t S = (n + TS - 1) / TS, J = (n + nb - 1) / nb;
+    // the substitution's diagonal blocks (size db, a multiple of nb: gb factor
+    // blocks each) are the dataflow's steps; the off-diagonal products go by
+    // factor block (each with its own strip factors)
+    const int64_t S = (n + TS - 1) / TS, J = (n + nb - 1) / nb, gb = db / nb;
     const int64_t sidx = LOWER ? (int64_t)blockIdx.x : S - 1 - (int64_t)blockIdx.x;
-    const int64_t j = sidx / (nb / TS);
+    const int64_t j = sidx / (db / TS);
+    const int64_t first = j * gb, last = (first + gb < J ? first + gb : J) - 1;
     const int64_t r0 = sidx * TS;
     const int rows = (int)(n - r0 < TS ? n - r0 : TS);
     unsigned* cnt = flags;
     unsigned* ready = flags + J;
     auto strips_of = [&](int64_t b) -> unsigned {
-        const int64_t kb = n - b * nb < nb ? n - b * nb : nb;
+        const int64_t kb = n - b * db < db ? n - b * db : db;
         return (unsigned)((kb + TS - 1) / TS);
     };
     if (tid < TS) w[tid] = (tid < rows) ? rhs[r0 + tid] : 0.0;
     const bool vload = vec && rows == TS;
     const int rg = lane % RG, cl = lane / RG;
     constexpr int PF = 16;                     // panel loads issued before the dependency's flag is awaited
-    for (int64_t i = LOWER ? 0 : J - 1; i != j; i += LOWER ? 1 : -1) {
+    for (int64_t i = LOWER ? 0 : J - 1; LOWER ? (i < first) : (i > last); i += LOWER ? 1 : -1) {
         const int64_t c0 = i * nb;
         const int kbi = (int)(n - c0 < nb ? n - c0 : nb);
         const int q = (kbi + 3) / 4, cb = wv * q, ce = (cb + q < kbi) ? cb + q : kbi;
@@ -160,7 +164,7 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
             const void* src = vload ? (const void*)(base + (int64_t)(c < ce ? c : 0) * lda) : (const void*)inv_all;
             pre[m] = *(const uint4*)src;
         }
-        if (!wait_flag(&ready[i], strips_of(i), err, &s_abort)) return;
+        if (!wait_flag(&ready[i / gb], strips_of(i / gb), err, &s_abort)) return;
 #pragma unroll
         for (int m = 0; m < PF; ++m) pin4(pre[m]);
         for (int c = tid; c < kbi; c += 256) zs[c] = get_shared(out + c0 + c);
@@ -208,13 +212,13 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
     // per lane with 16-byte loads, the waves splitting the columns.  They do
     // not depend on the other strips: the first batch is loaded while the
     // strips of the block meet.
-    const int64_t cj = j * nb;
-    const int kbj = (int)(n - cj < nb ? n - cj : nb);
+    const int64_t cj = j * db;
+    const int kbj = (int)(n - cj < db ? n - cj : db);
     const int rl0 = (int)(r0 - cj);
     const int clo = LOWER ? 0 : rl0, chi = LOWER ? (rl0 + TS < kbj ? rl0 + TS : kbj) : kbj;
     const int qv = (chi - clo + 3) / 4, cbv = clo + wv * qv, cev = (cbv + qv < chi) ? cbv + qv : chi;
     const int rsub = lane % 16, csub = lane / 16;
-    const float* colbase = inv_all + j * (int64_t)nb * nb + rl0 + 4 * rsub;
+    const float* colbase = inv_all + j * (int64_t)db * db + rl0 + 4 * rsub;
     // this strip's rows of the block right-hand side are final
     if (tid < rows) put_shared(tbuf + r0 + tid, w[tid]);
     signal_flag(&cnt[j]);
@@ -225,7 +229,7 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
 #pragma unroll
     for (int t = 0; t < NIV; ++t) {
         const int c = cbv + csub + 4 * t;
-        iv0[t] = *(const float4*)(colbase + (int64_t)(c < cev ? c : clo) * nb);
+        iv0[t] = *(const float4*)(colbase + (int64_t)(c < cev ? c : clo) * db);
     }
     if (!wait_flag(&cnt[j], strips_of(j), err, &s_abort)) return;
 #pragma unroll
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, const typename 
 #pragma unroll
             for (int t = 0; t < NIV; ++t) {
                 const int c = c0b + 4 * t;
-                iv[t] = *(const float4*)(colbase + (int64_t)(c < ce ? c : clo) * nb);
+                iv[t] = *(const float4*)(colbase + (int64_t)(c < ce ? c : clo) * db);
             }
 #pragma unroll
             for (int t = 0; t < NIV; ++t) {
@@ -322,10 +326,11 @@ static hipError_t prec_typed(const PrecPlan& p, const double* V, int64_t ldv, do
     hipEvent_t pt = prof::begin(prof::PREC, s);
     k_scale_rows<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, p.rowscale, V, ldv, R, nr);
     k_zero_u32<<<(unsigned)((fw * nr + 255) / 256), 256, 0, s>>>(flags, fw * nr);
-    k_trsv<ST, true><<<dim3((unsigned)S, (unsigned)nr), 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, vec,
+    const int db = (int)prec_block(nb);
+    k_trsv<ST, true><<<dim3((unsigned)S, (unsigned)nr), 256, 0, s>>>(n, (int)nb, db, (const T*)p.A, p.lda, vec,
                                                                      p.linv_full, p.lsc, nstrips32, R, n, Tb, Y, n,
                                                                      flags, fw, err);
-    k_trsv<ST, false><<<dim3((unsigned)S, (unsigned)nr), 256, 0, s>>>(n, (int)nb, (const T*)p.A, p.lda, vec,
+    k_trsv<ST, false><<<dim3((unsigned)S, (unsigned)nr), 256, 0, s>>>(n, (int)nb, db, (const T*)p.A, p.lda, vec,
                                                                       p.uinv_full, nullptr, nstrips32, Y, n, Tb, Z,
                                                                       ldz, flags + 2 * J, fw, err);
     prof::end(pt, prof::PREC, s, 2.0 * n * (double)n * nr, (double)n * n * sizeof(T) + 8.0 * n * nb);

@@ -18,7 +18,8 @@ which would absorb a wrong factor at the cost of extra iterations).
 3. Preconditioner apply: z = M^-1 v against an FP64 substitution with the
    GPU's own factor (FP32 diagonal blocks from aux, panels from the stored
    matrix with their strip scales undone), within the error of the FP32
-   diagonal-block inverses the apply uses.
+   inverses of the substitution's diagonal blocks (pairs of factor blocks
+   for nb <= 512) that the apply uses.
 """
 import threading
 
@@ -224,7 +225,11 @@ def test_preconditioner_apply_against_own_factor(n, nb, update, store):
     Z = mxp.mxp_apply_prec(fac, V).cpu().numpy()
     L, Uf = _dense_prec(prob, fac)
     LU = np.array(np.tril(L, -1) + Uf, order="F")
-    bound = 32 * nb * 2.0 ** -24
+    # FP32 inverses of the substitution's diagonal blocks: pairs of factor
+    # blocks (size 2 nb) for nb <= 512, their off-diagonal parts formed by
+    # two FP32 products
+    D = 2 * nb if nb <= 512 else nb
+    bound = 32 * D * 2.0 ** -24
     for r in range(2):
         want = oracle.lu_solve(LU, V[r].cpu().numpy())
         err = np.abs(Z[r] - want).max() / np.abs(want).max()
