@@ -65,7 +65,10 @@ AuxLayout aux_layout(int64_t n, int64_t nb);
 // diagonal-block size of the preconditioner's substitution: pairs of factor
 // blocks for nb <= 512 (one hand-over between work-groups per pair), the
 // factor blocks otherwise
-__host__ __device__ inline int64_t prec_block(int64_t nb) { return nb <= 512 ? 2 * nb : nb; }
+#ifndef MXP_PREC_PAIRS
+#define MXP_PREC_PAIRS 1
+#endif
+__host__ __device__ inline int64_t prec_block(int64_t nb) { return (MXP_PREC_PAIRS && nb <= 512) ? 2 * nb : nb; }
 int64_t operand_rows(int64_t n);
 WorkLayout work_layout(int64_t n, int64_t nb, int update);
 int dtype_bytes(int dt);

@@ -224,7 +224,10 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
     signal_flag(&cnt[j]);
     // (issued after the signal, whose wait for this wave's stores would also
     // wait for them)
-    constexpr int NIV = 16;
+#ifndef MXP_TRSV_NIV
+#define MXP_TRSV_NIV 16
+#endif
+    constexpr int NIV = MXP_TRSV_NIV;     // inverse loads in flight per lane (16 bytes each)
     float4 iv0[NIV];
 #pragma unroll
     for (int t = 0; t < NIV; ++t) {
