@@ -525,28 +525,50 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
 // product is one launch over all pairs (blockIdx.z = pair) of 64 x 64
 // output tiles on the FP32 matrix cores; the K range of a tile skips the
 // zero triangle of its triangular operand.
-constexpr int PP_SP = 96;   // LDS pitch of a staged 32 x 64 operand (two k rows fall in distinct banks)
+// LDS pitches of the staged operands (64 banks): A is written with the rows
+// running over the lanes and read two k rows at a time (pitch 96: the two
+// rows fall on distinct banks); B is written with k running over the lanes
+// (pitch 97, odd: 32 consecutive k rows on distinct banks)
+constexpr int PP_SP = 96, PP_SPB = 97;
 
-// acc (wave (wr, wc)'s 32 x 32 part of the 64 x 64 tile) += A[i0.., k] B[k, j0..] over k in [k_lo, k_hi)
+// acc (wave (wr, wc)'s 32 x 32 part of the 64 x 64 tile) += A[i0.., k] B[k, j0..] over k in [k_lo, k_hi);
+// the next chunk's operands are loaded into registers before this chunk's
+// products, so that their latency overlaps them
 template <class FA, class FB>
 MXP_DEV f16v_t pair_tile(FA fa, FB fb, int M, int N, int i0, int j0, int k_lo, int k_hi, float* sA, float* sB) {
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wr = wave & 1, wc = wave >> 1, lr = lane & 31, lh = lane >> 5;
     f16v_t acc = {};
+    float ra[8], rb[8];
+    auto fetch = [&](int k0) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = tid + 256 * t;
+            // loads without conditions (an index past the range reads a
+            // valid element, weighted zero): a load under a branch would
+            // wait for every load in flight
+            const int i = i0 + (e & 63), k = k0 + (e >> 6);          // A: rows contiguous
+            const float a = fa(i < M ? i : M - 1, k < k_hi ? k : k_hi - 1);
+            ra[t] = (i < M && k < k_hi) ? a : 0.0f;
+            const int kq = k0 + (e & 31), j = j0 + (e >> 5);         // B: k contiguous
+            const float b = fb(kq < k_hi ? kq : k_hi - 1, j < N ? j : N - 1);
+            rb[t] = (j < N && kq < k_hi) ? b : 0.0f;
+        }
+    };
+    if (k_lo < k_hi) fetch(k_lo);
     for (int k0 = k_lo; k0 < k_hi; k0 += 32) {
-        for (int e = tid; e < 2048; e += 256) {
-            const int r = e & 63, kk = e >> 6;            // A: rows contiguous
-            const int i = i0 + r, k = k0 + kk;
-            sA[kk * PP_SP + r] = (i < M && k < k_hi) ? fa(i, k) : 0.0f;
-            const int kb = e & 31, c = e >> 5;            // B: k contiguous
-            const int kq = k0 + kb, j = j0 + c;
-            sB[kb * PP_SP + c] = (j < N && kq < k_hi) ? fb(kq, j) : 0.0f;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const int e = tid + 256 * t;
+            sA[(e >> 6) * PP_SP + (e & 63)] = ra[t];
+            sB[(e & 31) * PP_SPB + (e >> 5)] = rb[t];
         }
         __syncthreads();
+        if (k0 + 32 < k_hi) fetch(k0 + 32);
 #pragma unroll
         for (int s2 = 0; s2 < 16; ++s2) {
             const int kk = 2 * s2 + lh;
-            acc = mfma2(sA[kk * PP_SP + wr * 32 + lr], sB[kk * PP_SP + wc * 32 + lr], acc);
+            acc = mfma2(sA[kk * PP_SP + wr * 32 + lr], sB[kk * PP_SPB + wc * 32 + lr], acc);
         }
         __syncthreads();
     }
@@ -571,7 +593,7 @@ template <int ST>
 __global__ __launch_bounds__(256) void k_pair_lower(int64_t n, int nb, const typename Store<ST>::T* __restrict__ A,
                                                     int64_t lda, const float* __restrict__ lsc, int64_t nstrips32,
                                                     float* __restrict__ inv_all, float* __restrict__ W, int phase) {
-    __shared__ float sA[32 * PP_SP], sB[32 * PP_SP];
+    __shared__ float sA[32 * PP_SP], sB[32 * PP_SPB];
     const int64_t p = blockIdx.z, D = 2 * (int64_t)nb;
     const int64_t k0 = p * D, k1 = k0 + nb;
     if (k1 >= n) return;
@@ -603,7 +625,7 @@ template <int ST>
 __global__ __launch_bounds__(256) void k_pair_upper(int64_t n, int nb, const typename Store<ST>::T* __restrict__ A,
                                                     int64_t lda, float* __restrict__ inv_all, float* __restrict__ W,
                                                     int phase) {
-    __shared__ float sA[32 * PP_SP], sB[32 * PP_SP];
+    __shared__ float sA[32 * PP_SP], sB[32 * PP_SPB];
     const int64_t p = blockIdx.z, D = 2 * (int64_t)nb;
     const int64_t k0 = p * D, k1 = k0 + nb;
     if (k1 >= n) return;
