@@ -156,40 +156,48 @@ template <class T> struct alignas(4 * sizeof(T)) Pack4 {
 // block, X_J = (S_J - sum_{I<J} X_I U_IJ) Uinv_J.  Urm: U11 row-major (ld),
 // uinv_rm: the 64x64 diagonal-block inverses, row-major.  The factor blocks
 // do not depend on the strip: block I+1 is loaded while block I is applied,
-// and the inverse block of step J is loaded when step J starts, so that a
-// step waits for one load latency instead of one per block.
+// and the first block and the inverse block of step J+1 are loaded while
+// step J finishes (its reductions and inverse product), so that a step
+// never starts with a load latency.
 MXP_DEV float strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ Urm, int ld,
                                    const float* __restrict__ uinv_rm, float* red) {
     float m = 0.0f;   // max |x| over this lane's final stores
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
+    const int k0 = kh * 32 + lh;
+    auto ld_iv = [&](float* v, int J) {
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) v[s2] = uinv_rm[(int64_t)J * 4096 + (k0 + 2 * s2) * 64 + blk * 32 + lr];
+    };
+    auto ld_blk = [&](float* bv, int I, int J) {
+        const int jc = J * 64 + blk * 32 + lr;
+        const int kb0 = I * 64 + k0;
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) bv[s2] = Urm[(int64_t)(kb0 + 2 * s2) * ld + jc];
+    };
+    float iv[16], ivn[16], b0[16], b1[16];
+    ld_iv(iv, 0);
     for (int J = 0; J < nbk; ++J) {
         const int jc = J * 64 + blk * 32 + lr;            // this lane's column of the output block
-        const int k0 = kh * 32 + lh;
-        float iv[16];
-#pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) iv[s2] = uinv_rm[(int64_t)J * 4096 + (k0 + 2 * s2) * 64 + blk * 32 + lr];
-        auto ld_blk = [&](float* bv, int I) {
-            const int kb0 = I * 64 + k0;
-#pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) bv[s2] = Urm[(int64_t)(kb0 + 2 * s2) * ld + jc];
-        };
         f16v_t acc = {};
         auto mf_blk = [&](const float* bv, int I) {
             const int kb0 = I * 64 + k0;
 #pragma unroll
             for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(S[lr * SP + kb0 + 2 * s2], bv[s2], acc);
         };
-        float b0[16], b1[16];
+        // b0 holds block (0, J) for J > 0 (loaded during step J - 1)
         int I = 0;
-        if (J > 0) ld_blk(b0, 0);
         for (; I + 1 < J; I += 2) {
-            ld_blk(b1, I + 1);
+            ld_blk(b1, I + 1, J);
             mf_blk(b0, I);
-            if (I + 2 < J) ld_blk(b0, I + 2);
+            if (I + 2 < J) ld_blk(b0, I + 2, J);
             mf_blk(b1, I + 1);
         }
         if (I < J) mf_blk(b0, I);
+        if (J + 1 < nbk) {
+            ld_blk(b0, 0, J + 1);
+            ld_iv(ivn, J + 1);
+        }
         khalf_reduce(acc, red, blk, kh, lane);
         if (kh == 0)
 #pragma unroll
@@ -210,6 +218,8 @@ MXP_DEV float strip_right_solve(float* S, int SP, int nbk, const float* __restri
                 m = fmaxf(m, fabsf(y[q]));
             }
         __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) iv[s2] = ivn[s2];
     }
     return strip_max(m, red);
 }
@@ -223,33 +233,39 @@ MXP_DEV float strip_left_solve(float* S, int SP, int nbk, const float* __restric
     float m = 0.0f;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
+    const int k0 = kh * 32 + lh;
+    auto ld_iv = [&](float* v, int I) {
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) v[s2] = linv[(int64_t)I * 4096 + (blk * 32 + lr) + 64 * (k0 + 2 * s2)];
+    };
+    auto ld_blk = [&](float* av, int J, int I) {
+        const int ir = I * 64 + blk * 32 + lr;
+        const int kb0 = J * 64 + k0;
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) av[s2] = T[ir + (int64_t)(kb0 + 2 * s2) * ld];
+    };
+    float iv[16], ivn[16], a0[16], a1[16];
+    ld_iv(iv, 0);
     for (int I = 0; I < nbk; ++I) {
-        const int ir = I * 64 + blk * 32 + lr;            // this lane's row of L for the A operand
-        const int k0 = kh * 32 + lh;
-        float iv[16];
-#pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) iv[s2] = linv[(int64_t)I * 4096 + (blk * 32 + lr) + 64 * (k0 + 2 * s2)];
-        auto ld_blk = [&](float* av, int J) {
-            const int kb0 = J * 64 + k0;
-#pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) av[s2] = T[ir + (int64_t)(kb0 + 2 * s2) * ld];
-        };
         f16v_t acc = {};
         auto mf_blk = [&](const float* av, int J) {
             const int kb0 = J * 64 + k0;
 #pragma unroll
             for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(av[s2], S[lr * SP + kb0 + 2 * s2], acc);
         };
-        float a0[16], a1[16];
+        // a0 holds block (I, 0) for I > 0 (loaded during step I - 1)
         int J = 0;
-        if (I > 0) ld_blk(a0, 0);
         for (; J + 1 < I; J += 2) {
-            ld_blk(a1, J + 1);
+            ld_blk(a1, J + 1, I);
             mf_blk(a0, J);
-            if (J + 2 < I) ld_blk(a0, J + 2);
+            if (J + 2 < I) ld_blk(a0, J + 2, I);
             mf_blk(a1, J + 1);
         }
         if (J < I) mf_blk(a0, J);
+        if (I + 1 < nbk) {
+            ld_blk(a0, 0, I + 1);
+            ld_iv(ivn, I + 1);
+        }
         khalf_reduce(acc, red, blk, kh, lane);
         if (kh == 0)
 #pragma unroll
@@ -270,6 +286,8 @@ MXP_DEV float strip_left_solve(float* S, int SP, int nbk, const float* __restric
                 m = fmaxf(m, fabsf(y[q]));
             }
         __syncthreads();
+#pragma unroll
+        for (int s2 = 0; s2 < 16; ++s2) iv[s2] = ivn[s2];
     }
     return strip_max(m, red);
 }
