@@ -296,55 +296,70 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(const DiagGroup grp) {
             for (int q = 0; q < 16; ++q) sA[res_col(q, lh) * TP + lr] = cv[q] - acc[q];
         }
         // LU in registers: lane r (and r + 32) holds row r.  The step loop
-        // stays rolled (small code: the kernel runs once per block, its
-        // instruction cache cold); the step's own column is read through
-        // the register index (s_set_gpr_idx).  Every step sweeps the columns
-        // from the step's range start on for the rows below the pivot: left of
-        // the diagonal a row then holds junk, never read again, and the
-        // multipliers go to sA (column j of L).
-        v32f x;
+        // stays rolled in blocks of four steps (small code: the kernel runs
+        // once per block, its instruction cache cold); the step's own column
+        // is read through the register index (s_set_gpr_idx).  Every step
+        // sweeps the columns from its block's start on for every row, with
+        // the multiplier zero for the rows at or above the pivot (which then
+        // stay as they are: no branch, no change of the execution mask); left
+        // of the diagonal a row then holds junk, never read again, and the
+        // multipliers go to mcol (column j of L, in registers).
+        // A zero or non-finite pivot spreads non-finite values into the rows
+        // above the later pivots too (their multiplier zero times a
+        // non-finite factor row), so the first bad pivot is recorded at its
+        // own step.
+        v32f x, mcol;
 #pragma unroll
-        for (int c = 0; c < 32; ++c) x[c] = sA[c * TP + lr];
+        for (int c = 0; c < 32; ++c) {
+            x[c] = sA[c * TP + lr];
+            mcol[c] = 0.0f;
+        }
+        int bad = -1;
         auto lu_step = [&](int j, auto C0) {
             const int lr = opaque(lane & 31);
             const float xj = x[j];
-            const float rp = __builtin_amdgcn_rcpf(rl(xj, j));   // v_rcp_f32 (1 ulp)
-            if (lr > j) {
-                // rows at or above the pivot stay as they are (readlane
-                // reads the pivot lane whatever the execution mask)
-                const float l = xj * rp;
+            const float pv = rl(xj, j);
+            if (bad < 0 && !(pv != 0.0f && isfinite(pv))) bad = j;
+            const float rp = __builtin_amdgcn_rcpf(pv);   // v_rcp_f32 (1 ulp)
+            const float l = (lr > j) ? xj * rp : 0.0f;
 #pragma unroll
-                for (int c = decltype(C0)::value; c < 32; ++c) x[c] = fmaf(-l, rl(x[c], j), x[c]);
-                if (lh == 0) sA[j * TP + lr] = l;
-            }
+            for (int c = decltype(C0)::value; c < 32; ++c) x[c] = fmaf(-l, rl(x[c], j), x[c]);
+            mcol[j] = l;
         };
 #pragma unroll 1
-        for (int j = 0; j < 8; ++j) lu_step(j, std::integral_constant<int, 0>());
+        for (int j = 0; j < 4; ++j) lu_step(j, std::integral_constant<int, 0>());
 #pragma unroll 1
-        for (int j = 8; j < 16; ++j) lu_step(j, std::integral_constant<int, 8>());
+        for (int j = 4; j < 8; ++j) lu_step(j, std::integral_constant<int, 4>());
 #pragma unroll 1
-        for (int j = 16; j < 24; ++j) lu_step(j, std::integral_constant<int, 16>());
+        for (int j = 8; j < 12; ++j) lu_step(j, std::integral_constant<int, 8>());
 #pragma unroll 1
-        for (int j = 24; j < 31; ++j) lu_step(j, std::integral_constant<int, 24>());
+        for (int j = 12; j < 16; ++j) lu_step(j, std::integral_constant<int, 12>());
+#pragma unroll 1
+        for (int j = 16; j < 20; ++j) lu_step(j, std::integral_constant<int, 16>());
+#pragma unroll 1
+        for (int j = 20; j < 24; ++j) lu_step(j, std::integral_constant<int, 20>());
+#pragma unroll 1
+        for (int j = 24; j < 28; ++j) lu_step(j, std::integral_constant<int, 24>());
+#pragma unroll 1
+        for (int j = 28; j < 31; ++j) lu_step(j, std::integral_constant<int, 28>());
         float* Cg = Tt(t, t);
         if (lh == 0) {
 #pragma unroll
             for (int c = 0; c < 32; ++c) {
-                const float f = (c >= lr) ? x[c] : sA[c * TP + lr];
+                const float f = (c >= lr) ? x[c] : mcol[c];
                 gst(Cg + lr + (int64_t)c * ldt, f);
                 sB[c * TP + lr] = f;
             }
         }
         complete(ph);
         store_final(t, t, sB);
-        // the pivots are the diagonal of U: report the first zero / non-finite one
-        int bad = -1;
-#pragma unroll
-        for (int c = 31; c >= 0; --c) {
-            const float d = rl(x[c], c);
-            if (32 * t + c < kb && !(d != 0.0f && isfinite(d))) bad = c;
+        // the last pivot; report the first zero / non-finite one (the
+        // identity padding beyond kb has pivots 1)
+        {
+            const float d = rl(x[31], 31);
+            if (bad < 0 && !(d != 0.0f && isfinite(d))) bad = 31;
         }
-        if (bad >= 0 && lane == 0) atomicMin(info, (unsigned long long)(k + 32 * t + bad + 1));
+        if (bad >= 0 && 32 * t + bad < kb && lane == 0) atomicMin(info, (unsigned long long)(k + 32 * t + bad + 1));
     };
 
     // the inverse of the unit-lower factor of tile (t,t), as block (t&1, t&1)
