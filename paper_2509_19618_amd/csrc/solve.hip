@@ -146,25 +146,37 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
     const bool vload = vec && rows == TS;
     const int rg = lane % RG, cl = lane / RG;
     constexpr int PF = 16;                     // panel loads issued before the dependency's flag is awaited
-    for (int64_t i = LOWER ? 0 : J - 1; LOWER ? (i < first) : (i > last); i += LOWER ? 1 : -1) {
+    // The factor panels do not depend on the flags: the panel of the next
+    // dependency block is loaded while the current one is awaited and applied
+    // (two buffers, the loop taken two blocks at a time).  The loads carry no
+    // condition (a column past the range reads column 0 and is weighted zero
+    // below): a load under a branch ends in a wait for every load in flight,
+    // which would serialise them (the ragged last strip, which takes element
+    // loads below, reads the 16-byte aligned inverse array instead and
+    // ignores the values).
+    const int64_t istep = LOWER ? 1 : -1;
+    auto in_range = [&](int64_t i) { return LOWER ? (i < first) : (i > last); };
+    auto issue = [&](int64_t i, uint4* dst) {
         const int64_t c0 = i * nb;
         const int kbi = (int)(n - c0 < nb ? n - c0 : nb);
         const int q = (kbi + 3) / 4, cb = wv * q, ce = (cb + q < kbi) ? cb + q : kbi;
         const T* base = A + r0 + RPL * rg + c0 * lda;
-        // the factor panel does not depend on the flag: its loads overlap the
-        // wait.  The loads carry no condition (a column past the range reads
-        // column 0 and is weighted zero below): a load under a branch ends in
-        // a wait for every load in flight, which would serialise them
-        // (the ragged last strip, which takes element loads below, reads the
-        // 16-byte aligned inverse array instead and ignores the values)
-        uint4 pre[PF];
 #pragma unroll
         for (int m = 0; m < PF; ++m) {
             const int c = cb + cl + m * CPI;
             const void* src = vload ? (const void*)(base + (int64_t)(c < ce ? c : 0) * lda) : (const void*)inv_all;
-            pre[m] = *(const uint4*)src;
+            dst[m] = *(const uint4*)src;
         }
-        if (!wait_flag(&ready[i / gb], strips_of(i / gb), err, &s_abort)) return;
+    };
+    // one dependency block: wait for it, multiply its panel (prefetched in
+    // pre) with its solution and subtract from w
+    auto dep = [&](int64_t i, uint4* pre, uint4* nxt) -> bool {
+        const int64_t c0 = i * nb;
+        const int kbi = (int)(n - c0 < nb ? n - c0 : nb);
+        const int q = (kbi + 3) / 4, cb = wv * q, ce = (cb + q < kbi) ? cb + q : kbi;
+        const T* base = A + r0 + RPL * rg + c0 * lda;
+        if (in_range(i + istep)) issue(i + istep, nxt);
+        if (!wait_flag(&ready[i / gb], strips_of(i / gb), err, &s_abort)) return false;
 #pragma unroll
         for (int m = 0; m < PF; ++m) pin4(pre[m]);
         for (int c = tid; c < kbi; c += 256) zs[c] = get_shared(out + c0 + c);
@@ -205,6 +217,20 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
                 for (int v2 = 0; v2 < CPI; ++v2) t += part[u][v2][tid];
             if (LOWER) t /= (double)lsc[i * nstrips32 + (r0 + tid) / 32];
             w[tid] -= t;
+        }
+        return true;
+    };
+    {
+        uint4 pa[PF], pb[PF];
+        int64_t i = LOWER ? 0 : J - 1;
+        if (in_range(i)) issue(i, pa);
+        for (;;) {
+            if (!in_range(i)) break;
+            if (!dep(i, pa, pb)) return;
+            i += istep;
+            if (!in_range(i)) break;
+            if (!dep(i, pb, pa)) return;
+            i += istep;
         }
     }
     // this strip's rows of the diagonal-block inverse (lower / upper
