@@ -126,13 +126,17 @@ int mxp_generate(int64_t n, int64_t nrhs, uint64_t seed, int kind, double gamma,
  * (MXP_F16, MXP_BF16, MXP_F8E4M3 with a power-of-two scale per strip of
  * rows of L21 / columns of U12; MXP_F32 for an all-FP32 factorisation);
  * the trailing matrix is updated A22 <- A22 - L21 U12 on the matrix cores
- * with FP32 accumulation and stored back in `store`.
+ * with FP32 accumulation and stored back in `store`.  The updates of block
+ * steps k and k+1 (k an even block index) reach everything beyond block
+ * k+1 in one pass: their sum is accumulated in FP32 and rounded to `store`
+ * once; block column and row k+1 receive step k's update alone.
  *
  * On return A holds L (unit lower, strictly below the diagonal; blocks of
  * L21 stored multiplied by their power-of-two scale) and U (upper) in the
- * storage format, and `aux` holds what the solve needs: FP32 inverses of
- * the 64x64 diagonal sub-blocks of every L11 and U11, the per-strip scales
- * of the stored L21, and the FP64 row scaling.
+ * storage format, and `aux` holds what the solve needs: the FP32 diagonal
+ * blocks, FP32 inverses of the preconditioner's diagonal blocks (pairs of
+ * factor blocks for nb <= 512) and of the 64x64 diagonal sub-blocks, the
+ * per-strip scales of the stored L21, and the FP64 row scaling.
  *
  * Valid (update, store) pairs: (F32,F32), (F16,F16), (BF16,BF16),
  * (F8E4M3,F16), (F8E4M3,BF16), (F16,F32), (BF16,F32).
@@ -141,8 +145,10 @@ int mxp_generate(int64_t n, int64_t nrhs, uint64_t seed, int kind, double gamma,
  * mxp_factor_aux_bytes / mxp_factor_work_bytes give the sizes of `aux`
  * (kept until the last solve) and `work` (scratch during the call).
  * `scaling`: MXP_SCALE_NONE, or MXP_SCALE_ROW_EQUIL which first scales
- * row i of A in place by the power of two nearest 1/diag[i] (diag = the
- * exact FP64 diagonal from mxp_generate, required then, else may be NULL)
+ * row i of A in place by 2^t / p_i, p_i the power of two nearest diag[i]
+ * (t = 14 for FP16 storage, keeping the off-diagonal entries in FP16's
+ * normal range, 0 otherwise; diag = the exact FP64 diagonal from
+ * mxp_generate, required then, else may be NULL)
  * and records the factors in `aux`; the solve applies the same scaling to
  * its vectors, so X solves the original, unscaled system.
  * `info` (host pointer, may be NULL): if non-NULL the call synchronises
@@ -167,13 +173,16 @@ int mxp_factor(int64_t n, int64_t nb, int update, int store, int scaling, const 
  * mxp_factor_group -- the factorisations of up to 8 independent matrices of
  * the same formats in lockstep on one stream (the batched launches of the
  * solve server; not in the paper): per block step ONE launch factors the
- * diagonal blocks of all of them, ONE launch forms all their strip TRSMs
- * and ONE launch updates all their trailing matrices, each kernel finding
- * its matrix through a descriptor array.  Sizes and block sizes may differ;
+ * diagonal blocks of all of them, ONE launch forms all their strip TRSMs,
+ * and per pair of block steps ONE launch updates all their next block
+ * columns and rows and ONE all their trailing matrices (the two steps
+ * merged, as in mxp_factor), each kernel finding its matrix through a
+ * descriptor array.  Sizes and block sizes may differ;
  * no look-ahead.  Each item's A, aux and work are as for mxp_factor (no
  * scaling); the results are those of mxp_factor bit for bit.
  * tile: the work-group tile of the trailing update, MXP_TILE_256x128 (the
- *   one mxp_factor uses) or MXP_TILE_128x128 (twice the tiles: small n).
+ *   one mxp_factor uses for launches of at least one tile per CU) or
+ *   MXP_TILE_128x128 (twice the tiles: small n).
  * info: host array of count entries (may be NULL: asynchronous), as for
  *   mxp_factor; MXP_ESINGULAR if any matrix had a bad pivot.
  */

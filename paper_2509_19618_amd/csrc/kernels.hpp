@@ -122,12 +122,13 @@ hipError_t diag_lu_group(int store, const DiagCall* calls, int count, hipStream_
 hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,
                    float* linv, float* uinv, int* sync, unsigned long long* info, hipStream_t s);
 hipError_t row_equilibrate(const FactorPlan& p, const double* diag, hipStream_t s);
-// Side stream and events of the look-ahead (default stream priority).  A
-// factorisation uses the caller's context, or a per-device one if la is NULL;
-// concurrent factorisations need a context each.
-// the critical stream of a factorisation (diagonal-block update, LU, strip
-// TRSMs) and the events that order it against the caller's stream (cross
-// update, rest of the trailing update)
+// Side stream and events of the look-ahead (default stream priority): the
+// side stream carries the chain of a factorisation (diagonal-block update,
+// LU, strip TRSMs, the next block column and row by one step); the events
+// order it against the caller's stream, which runs the merged updates
+// (ev_upd: the last part of a pair's update, ev_cross / ev_next: its first
+// two parts, ev_panel: the panels of the next pair).  A factorisation uses
+// the caller's context, or one from a per-device pool if la is NULL.
 struct Lookahead {
     hipStream_t side = nullptr;
     hipEvent_t ev_upd = nullptr, ev_cross = nullptr, ev_next = nullptr, ev_panel = nullptr;
@@ -136,8 +137,10 @@ hipError_t lookahead_create(Lookahead* la);
 void lookahead_destroy(Lookahead* la);
 hipError_t factor_run(const FactorPlan& p, hipStream_t s, Lookahead* la = nullptr);
 // up to GEMM_GROUP_MAX factorisations (same formats, any sizes) in lockstep on
-// one stream: per block step one launch each of the diagonal-block LUs, the
-// strip TRSMs and the trailing updates of all of them (no look-ahead)
+// one stream: per block step one launch each of the diagonal-block LUs and
+// the strip TRSMs of all of them, and per pair of steps one launch of the
+// next block column / row updates and one of the merged updates (no
+// look-ahead; the arithmetic of factor_run)
 hipError_t factor_group(const FactorPlan* plans, int count, hipStream_t s);
 // mxp_factor with an explicit look-ahead context (api.hip)
 int factor_with(int64_t n, int64_t nb, int update, int store, int scaling, const double* diag, void* A, int64_t lda,
