@@ -69,6 +69,15 @@ def test_argument_errors_return_einval_without_device_work():
     assert L.mxp_factor(64, 64, mxp.F16, mxp.F16, 0, None, fake, 64, fake, fake, 16, None, None) == mxp.EWORKSPACE
     # row equilibration without the diagonal
     assert L.mxp_factor(64, 64, mxp.F16, mxp.F16, 1, None, fake, 64, fake, fake, 1 << 30, None, None) == mxp.EINVAL
+    # the two-step update: a second segment of zero or ragged length, a bad format pair
+    f = fake
+    assert L.mxp_trailing_update2(64, 64, 64, 0, mxp.F16, mxp.F16, f, 64, f, f, f, f, f, f, f, f, None) == mxp.EINVAL
+    assert L.mxp_trailing_update2(64, 64, 64, 48, mxp.F16, mxp.F16, f, 64, f, f, f, f, f, f, f, f, None) == mxp.EINVAL
+    assert L.mxp_trailing_update2(64, 64, 64, 64, mxp.F16, mxp.BF16, f, 64, f, f, f, f, f, f, f, f, None) == mxp.EINVAL
+    assert L.mxp_trailing_update2(64, 64, 64, 64, mxp.F16, mxp.F16, f, 64, f, f, f, f, None, f, f, f, None) == mxp.EINVAL
+    # nothing to update: no device work, no error
+    assert L.mxp_trailing_update2(0, 64, 64, 64, mxp.F16, mxp.F16, None, 1, None, None, None, None, None, None, None,
+                                  None, None) == mxp.OK
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
