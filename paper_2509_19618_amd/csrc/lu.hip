@@ -128,6 +128,10 @@ constexpr int SR = 32;  // rows (columns) per strip of L21 (U12) and per scale
 // column l%32.  The strip lives in LDS (pitch odd, so the 32 rows / columns
 // a fragment touches fall in distinct banks); the factor blocks stream from
 // L2 straight into operand registers along contiguous runs.
+// v, treated as written here: a batch of LDS reads feeding an MFMA chain
+// completes before the chain (one wait), instead of one wait per product
+MXP_DEV void pin_f(float& v) { asm volatile("" : "+v"(v)); }
+
 // add the other K-half's partial results (waves 2,3 -> waves 0,1) through LDS
 MXP_DEV void khalf_reduce(f16v_t& acc, float* red, int blk, int kh, int lane) {
     if (kh == 1)
@@ -162,18 +166,21 @@ template <class T> struct alignas(4 * sizeof(T)) Pack4 {
 MXP_DEV float strip_right_solve(float* S, int SP, int nbk, const float* __restrict__ Urm, int ld,
                                    const float* __restrict__ uinv_rm, float* red) {
     float m = 0.0f;   // max |x| over this lane's final stores
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
     const int k0 = kh * 32 + lh;
     auto ld_iv = [&](float* v, int J) {
 #pragma unroll
         for (int s2 = 0; s2 < 16; ++s2) v[s2] = uinv_rm[(int64_t)J * 4096 + (k0 + 2 * s2) * 64 + blk * 32 + lr];
     };
+    // a block's sixteen loads: a wave-uniform base (kept in scalar
+    // registers) plus one 32-bit lane offset
+    const int ld2 = 2 * ld;
     auto ld_blk = [&](float* bv, int I, int J) {
-        const int jc = J * 64 + blk * 32 + lr;
-        const int kb0 = I * 64 + k0;
+        const float* ub = Urm + (int64_t)(I * 64 + kh * 32) * ld + J * 64 + blk * 32;
+        const int lo = lh * ld + lr;
 #pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) bv[s2] = Urm[(int64_t)(kb0 + 2 * s2) * ld + jc];
+        for (int s2 = 0; s2 < 16; ++s2) bv[s2] = ub[s2 * ld2 + lo];
     };
     float iv[16], ivn[16], b0[16], b1[16];
     ld_iv(iv, 0);
@@ -182,8 +189,13 @@ MXP_DEV float strip_right_solve(float* S, int SP, int nbk, const float* __restri
         f16v_t acc = {};
         auto mf_blk = [&](const float* bv, int I) {
             const int kb0 = I * 64 + k0;
+            float av[16];
 #pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(S[lr * SP + kb0 + 2 * s2], bv[s2], acc);
+            for (int s2 = 0; s2 < 16; ++s2) av[s2] = S[lr * SP + kb0 + 2 * s2];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) pin_f(av[s2]);
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(av[s2], bv[s2], acc);
         };
         // b0 holds block (0, J) for J > 0 (loaded during step J - 1)
         int I = 0;
@@ -207,8 +219,15 @@ MXP_DEV float strip_right_solve(float* S, int SP, int nbk, const float* __restri
             }
         __syncthreads();
         f16v_t y = {};
+        {
+            float av[16];
 #pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) y = mfma2(S[lr * SP + J * 64 + k0 + 2 * s2], iv[s2], y);
+            for (int s2 = 0; s2 < 16; ++s2) av[s2] = S[lr * SP + J * 64 + k0 + 2 * s2];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) pin_f(av[s2]);
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) y = mfma2(av[s2], iv[s2], y);
+        }
         khalf_reduce(y, red, blk, kh, lane);
         if (kh == 0)
 #pragma unroll
@@ -231,18 +250,19 @@ MXP_DEV float strip_right_solve(float* S, int SP, int nbk, const float* __restri
 MXP_DEV float strip_left_solve(float* S, int SP, int nbk, const float* __restrict__ T, int ld,
                                   const float* __restrict__ linv, float* red) {
     float m = 0.0f;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lr = lane & 31, lh = lane >> 5, blk = wave & 1, kh = wave >> 1;
     const int k0 = kh * 32 + lh;
     auto ld_iv = [&](float* v, int I) {
 #pragma unroll
         for (int s2 = 0; s2 < 16; ++s2) v[s2] = linv[(int64_t)I * 4096 + (blk * 32 + lr) + 64 * (k0 + 2 * s2)];
     };
+    const int ld2 = 2 * ld;
     auto ld_blk = [&](float* av, int J, int I) {
-        const int ir = I * 64 + blk * 32 + lr;
-        const int kb0 = J * 64 + k0;
+        const float* ub = T + I * 64 + blk * 32 + (int64_t)(J * 64 + kh * 32) * ld;
+        const int lo = lr + lh * ld;
 #pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) av[s2] = T[ir + (int64_t)(kb0 + 2 * s2) * ld];
+        for (int s2 = 0; s2 < 16; ++s2) av[s2] = ub[s2 * ld2 + lo];
     };
     float iv[16], ivn[16], a0[16], a1[16];
     ld_iv(iv, 0);
@@ -250,8 +270,13 @@ MXP_DEV float strip_left_solve(float* S, int SP, int nbk, const float* __restric
         f16v_t acc = {};
         auto mf_blk = [&](const float* av, int J) {
             const int kb0 = J * 64 + k0;
+            float bv[16];
 #pragma unroll
-            for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(av[s2], S[lr * SP + kb0 + 2 * s2], acc);
+            for (int s2 = 0; s2 < 16; ++s2) bv[s2] = S[lr * SP + kb0 + 2 * s2];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) pin_f(bv[s2]);
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) acc = mfma2(av[s2], bv[s2], acc);
         };
         // a0 holds block (I, 0) for I > 0 (loaded during step I - 1)
         int J = 0;
@@ -275,8 +300,15 @@ MXP_DEV float strip_left_solve(float* S, int SP, int nbk, const float* __restric
             }
         __syncthreads();
         f16v_t y = {};
+        {
+            float bv[16];
 #pragma unroll
-        for (int s2 = 0; s2 < 16; ++s2) y = mfma2(iv[s2], S[lr * SP + I * 64 + k0 + 2 * s2], y);
+            for (int s2 = 0; s2 < 16; ++s2) bv[s2] = S[lr * SP + I * 64 + k0 + 2 * s2];
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) pin_f(bv[s2]);
+#pragma unroll
+            for (int s2 = 0; s2 < 16; ++s2) y = mfma2(iv[s2], bv[s2], y);
+        }
         khalf_reduce(y, red, blk, kh, lane);
         if (kh == 0)
 #pragma unroll
