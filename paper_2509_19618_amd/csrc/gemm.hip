@@ -109,7 +109,10 @@ template <> struct Quad<BF16> {
 // MFMA loop; TMv = 128 gives twice as many tiles for small trailing matrices.
 constexpr int TN = 128;
 constexpr int GBK = 64;            // K bytes per stage
-constexpr int NBUF = 3;            // stages in LDS: two copies in flight while one is read
+#ifndef MXP_NBUF
+#define MXP_NBUF 3
+#endif
+constexpr int NBUF = MXP_NBUF;     // stages in LDS: two copies in flight while one is read
 constexpr int GCH = GBK / 16;      // 16-byte chunks per operand row
 constexpr int SB = TN * GBK;       // bytes of one B stage
 constexpr int GGROUP = 8;          // tile rows per group in the tile order
