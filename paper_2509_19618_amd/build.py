@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmxp.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "obj")
-SOURCES = ["api.hip", "gen.hip", "lu.hip", "diag.hip", "solve.hip", "prof.hip", "gemm.hip", "server.hip", "lu64.hip"]
+SOURCES = ["api.hip", "gen.hip", "lu.hip", "panel.hip", "diag.hip", "solve.hip", "prof.hip", "gemm.hip", "server.hip", "lu64.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -114,12 +114,16 @@ static FactorPlan make_plan(int64_t n, int64_t nb, int update, int store, void* 
         p.info = (unsigned long long*)(w + wl.info);
         p.dsync = (int*)(w + wl.dsync);
         p.pairw = (float*)(w + wl.pairw);
+        p.binv = w + wl.binv;
+        p.binv_sc = (float*)(w + wl.binv_sc);
     } else {
         p.Lq = p.Uq = nullptr;
         p.inv_sa = p.inv_sb = nullptr;
         p.info = nullptr;
         p.dsync = nullptr;
         p.pairw = nullptr;
+        p.binv = nullptr;
+        p.binv_sc = nullptr;
     }
     return p;
 }

@@ -50,6 +50,8 @@ struct FactorPlan {
     float* inv_sa;   // 4 sets of op_rows/32
     float* inv_sb;   // 4 sets of op_rows/32
     float* pairw;    // ceil(n / 2nb) x nb x nb: scratch of the pair inverses (D = 2 nb only)
+    void* binv;      // 2 x 3 x nb x nb 16-bit parts of the current block's inverses (U11^-1, L11^-1)
+    float* binv_sc;  // 2 x nb reciprocal line scales of those parts
     unsigned long long* info;  // 1
     int* dsync;      // nblk x diag_sync_words(): phase counters of the diagonal-block LUs (zeroed per factorisation)
     int gemm_tile = 0;  // work-group tile of the trailing update (GEMM_TILE_*)
@@ -59,7 +61,7 @@ struct AuxLayout {
     size_t T, Trm, linv, uinv, lsc, rowscale, linv_full, uinv_full, total;
 };
 struct WorkLayout {
-    size_t Lq, Uq, inv_sa, inv_sb, info, dsync, pairw, total;
+    size_t Lq, Uq, inv_sa, inv_sb, info, dsync, pairw, binv, binv_sc, total;
 };
 AuxLayout aux_layout(int64_t n, int64_t nb);
 // diagonal-block size of the preconditioner's substitution: pairs of factor
@@ -117,6 +119,39 @@ struct DiagCall {
     int* sync;
     unsigned long long* info;
 };
+// Strip solves through the diagonal block's inverses (16-bit storage,
+// panel.hip): per block step, (1) block_inverses: the full FP32 inverses of
+// L11 and U11 (the preconditioner's diagonal blocks, formed once here);
+// (2) panel_split: each inverse split into 16-bit parts of the storage format
+// under a power-of-two scale per line; (3) panel_trsm: L21 = A21 U11^-1 and
+// U12 = L11^-1 A12 on the 16-bit matrix cores with FP32 accumulation, fused
+// with the rounding to the update format under a power-of-two strip scale.
+// One launch of each serves a group of factorisations: every kernel finds
+// its descriptor by its work-group number (cumulative ends per kernel).
+struct PanelOne {
+    void* A;
+    int64_t lda, n, k, ldi;
+    int nb, kbp, ntile, pad;                 // ntile: output tiles of panel_rows(launch nb) per side
+    int wg_inv, wg_split, wg_trsm, pad2;
+    const float *T, *Trm, *linv, *uinv;      // the block's FP32 factor and 64x64 sub-block inverses
+    float *Li, *Ui;                          // the block's FP32 inverses (column-major, ld ldi)
+    void *lb, *ub;                           // their 16-bit parts
+    float *lbs, *ubs;                        // reciprocal line scales of the parts
+    void* Lq;
+    float* inv_sa;
+    float* lsc_blk;
+    void* Uq;
+    float* inv_sb;
+};
+struct PanelGroup {
+    PanelOne g[GEMM_GROUP_MAX];
+    int count;
+};
+bool panel_path(int store);                  // FP16 and BF16 storage
+int panel_rows(int store, int nb);           // rows (columns) of an output tile of panel_trsm
+hipError_t block_inverses(const PanelGroup& grp, int wg, int nbmax, hipStream_t s);
+hipError_t panel_split(int store, const PanelGroup& grp, int wg, int nbmax, hipStream_t s);
+hipError_t panel_trsm(int store, int update, const PanelGroup& grp, int wg, int nbmax, hipStream_t s);
 // the diagonal-block LUs of up to GEMM_GROUP_MAX factorisations in one launch
 hipError_t diag_lu_group(int store, const DiagCall* calls, int count, hipStream_t s);
 hipError_t diag_lu(int store, void* A, int64_t lda, int64_t k, int kb, int kbp, float* T, float* Trm, int ldt,

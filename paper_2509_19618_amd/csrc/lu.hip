@@ -69,6 +69,8 @@ WorkLayout work_layout(int64_t n, int64_t nb, int update) {
     W.dsync = off; off = al256(off + (size_t)((n + nb - 1) / nb) * diag_sync_words() * 4);
     W.pairw = off;
     if (prec_block(nb) == 2 * nb) off = al256(off + (size_t)((n + 2 * nb - 1) / (2 * nb)) * nb * nb * 4);
+    W.binv = off; off = al256(off + (size_t)2 * 3 * nb * nb * 2);
+    W.binv_sc = off; off = al256(off + (size_t)2 * nb * 4);
     W.total = off;
     return W;
 }
@@ -510,18 +512,12 @@ __global__ __launch_bounds__(256) void k_trsm(const TrsmGroup grp) {
                              w - G.nstrip);
 }
 
-// Full inverses of the diagonal blocks (for the preconditioner), all blocks
-// in one launch: blockIdx.y = block, blockIdx.x = 32-wide strip.
-// U11^-1 rows r0..r0+31 = I[r0:r0+32, :] U11^-1; L11^-1 columns = L11^-1 I[:, c0:c0+32].
-__global__ __launch_bounds__(256) void k_inv_upper(int64_t n, int nb, const float* __restrict__ Trm_all,
-                                                   const float* __restrict__ uinv_all, float* __restrict__ out_all) {
-    extern __shared__ float smem[];
-    const int64_t blk = blockIdx.y;
-    const int64_t k = blk * nb;
-    const int kb = (int)(n - k < nb ? n - k : nb);
-    const int kbp = (kb + 63) / 64 * 64;
-    const int r0 = SR * blockIdx.x;
-    if (r0 >= kbp) return;
+// Full FP32 inverses of a diagonal block (size kbp) by strips of 32:
+// U11^-1 rows r0..r0+31 = I[r0:r0+32, :] U11^-1 (right solve with Trm, the
+// factor row-major), L11^-1 columns c0..c0+31 = L11^-1 I[:, c0:c0+32] (left
+// solve with T, column-major); out: the inverse, column-major, ld D.
+MXP_DEV void inv_upper_strip(int kbp, const float* __restrict__ Trm, int ld, const float* __restrict__ uinv,
+                             float* __restrict__ out, int64_t D, int r0, float* smem) {
     const int SP = kbp + 1;
     float* S = smem;
     float* red = smem + SR * SP;
@@ -530,25 +526,14 @@ __global__ __launch_bounds__(256) void k_inv_upper(int64_t n, int nb, const floa
         S[ii * SP + c] = (r0 + ii == c) ? 1.0f : 0.0f;
     }
     __syncthreads();
-    strip_right_solve(S, SP, kbp / 64, Trm_all + blk * nb * nb, nb, uinv_all + blk * nb * 64, red);
-    // block blk is diagonal block blk % g of group blk / g (column-major, ld D)
-    const int64_t D = prec_block(nb), g = D / nb, o = (blk % g) * nb;
-    float* out = out_all + (blk / g) * D * D + o + o * D;
+    strip_right_solve(S, SP, kbp / 64, Trm, ld, uinv, red);
     for (int e = threadIdx.x; e < SR * kbp; e += 256) {
         int ii = e % SR, c = e / SR;
         out[(r0 + ii) + (int64_t)c * D] = S[ii * SP + c];
     }
 }
-
-__global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const float* __restrict__ Tall,
-                                                   const float* __restrict__ linv_all, float* __restrict__ out_all) {
-    extern __shared__ float smem[];
-    const int64_t blk = blockIdx.y;
-    const int64_t k = blk * nb;
-    const int kb = (int)(n - k < nb ? n - k : nb);
-    const int kbp = (kb + 63) / 64 * 64;
-    const int c0 = SR * blockIdx.x;
-    if (c0 >= kbp) return;
+MXP_DEV void inv_lower_strip(int kbp, const float* __restrict__ T, int ld, const float* __restrict__ linv,
+                             float* __restrict__ out, int64_t D, int c0, float* smem) {
     const int SP = kbp + 1;
     float* S = smem;
     float* red = smem + SR * SP;
@@ -557,13 +542,68 @@ __global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, const floa
         S[cc * SP + kk] = (kk == c0 + cc) ? 1.0f : 0.0f;
     }
     __syncthreads();
-    strip_left_solve(S, SP, kbp / 64, Tall + blk * nb * nb, nb, linv_all + blk * nb * 64, red);
-    const int64_t D = prec_block(nb), g = D / nb, o = (blk % g) * nb;
-    float* out = out_all + (blk / g) * D * D + o + o * D;
+    strip_left_solve(S, SP, kbp / 64, T, ld, linv, red);
     for (int e = threadIdx.x; e < SR * kbp; e += 256) {
         int kk = e % kbp, cc = e / kbp;
         out[kk + (int64_t)(c0 + cc) * D] = S[cc * SP + kk];
     }
+}
+
+// the inverses of diagonal blocks blk0.. in one launch (after the
+// factorisation: every block with FP32 storage, the blocks whose strips were
+// solved by substitution otherwise); blockIdx.y = block - blk0, blockIdx.x = strip.  Block blk is
+// diagonal block blk % g of the preconditioner's group blk / g
+// (column-major, ld D).
+__global__ __launch_bounds__(256) void k_inv_upper(int64_t n, int nb, int64_t blk0, const float* __restrict__ Trm_all,
+                                                   const float* __restrict__ uinv_all, float* __restrict__ out_all) {
+    extern __shared__ float smem[];
+    const int64_t blk = blk0 + blockIdx.y;
+    const int64_t k = blk * nb;
+    const int kb = (int)(n - k < nb ? n - k : nb);
+    const int kbp = (kb + 63) / 64 * 64;
+    const int r0 = SR * blockIdx.x;
+    if (r0 >= kbp) return;
+    const int64_t D = prec_block(nb), g = D / nb, o = (blk % g) * nb;
+    inv_upper_strip(kbp, Trm_all + blk * nb * nb, nb, uinv_all + blk * nb * 64,
+                    out_all + (blk / g) * D * D + o + o * D, D, r0, smem);
+}
+
+__global__ __launch_bounds__(256) void k_inv_lower(int64_t n, int nb, int64_t blk0, const float* __restrict__ Tall,
+                                                   const float* __restrict__ linv_all, float* __restrict__ out_all) {
+    extern __shared__ float smem[];
+    const int64_t blk = blk0 + blockIdx.y;
+    const int64_t k = blk * nb;
+    const int kb = (int)(n - k < nb ? n - k : nb);
+    const int kbp = (kb + 63) / 64 * 64;
+    const int c0 = SR * blockIdx.x;
+    if (c0 >= kbp) return;
+    const int64_t D = prec_block(nb), g = D / nb, o = (blk % g) * nb;
+    inv_lower_strip(kbp, Tall + blk * nb * nb, nb, linv_all + blk * nb * 64,
+                    out_all + (blk / g) * D * D + o + o * D, D, c0, smem);
+}
+
+// the inverses of one block step's diagonal blocks (16-bit storage: formed
+// right after each diagonal-block LU, they serve the strip products and
+// later the preconditioner): work-groups [0, kbp/32) of a descriptor solve
+// the strips of L11^-1, the next kbp/32 those of U11^-1
+__global__ __launch_bounds__(256) void k_block_inv(const PanelGroup grp) {
+    extern __shared__ float smem[];
+    int d = 0;
+    while ((int)blockIdx.x >= grp.g[d].wg_inv) ++d;
+    const PanelOne& G = grp.g[d];
+    const int w0 = (int)blockIdx.x - (d > 0 ? grp.g[d - 1].wg_inv : 0);
+    const int nstr = G.kbp / SR;
+    if (w0 < nstr) inv_lower_strip(G.kbp, G.T, G.nb, G.linv, G.Li, G.ldi, SR * w0, smem);
+    else inv_upper_strip(G.kbp, G.Trm, G.nb, G.uinv, G.Ui, G.ldi, SR * (w0 - nstr), smem);
+}
+
+hipError_t block_inverses(const PanelGroup& grp, int wg, int nbmax, hipStream_t s) {
+    static const hipError_t attr = hipFuncSetAttribute((const void*)k_block_inv,
+                                                       hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                       (int)trsm_smem(1024));
+    if (attr) return attr;
+    k_block_inv<<<wg, 256, trsm_smem(nbmax), s>>>(grp);
+    return hipGetLastError();
 }
 
 // Off-diagonal blocks of the inverses of the pairs of diagonal blocks
@@ -701,14 +741,39 @@ __global__ __launch_bounds__(256) void k_pair_upper(int64_t n, int nb, const typ
 // the full FP32 inverses of the preconditioner's diagonal blocks (after the
 // factorisation): every factor block's, then the off-diagonal blocks of the
 // pairs.  W: scratch of ceil(n / 2nb) nb^2 floats.
+// Block step k solves its strips through the block inverses (16-bit storage)
+// while the trailing part is at least MXP_PANEL_MIN blocks: there the
+// products free the compute units the substitution would hold beside the
+// merged update; the last steps, bound by the chain of panel solves, keep the
+// substitution, whose latency is lower.  Depends on (n, nb, k) alone, so that
+// grouped and single factorisations take the same path.
+#ifndef MXP_PANEL_MIN
+#define MXP_PANEL_MIN 16
+#endif
+static bool inverse_path(const FactorPlan& p, int64_t k) {
+    const int64_t kb = p.n - k < p.nb ? p.n - k : p.nb;
+    return panel_path(p.store) && p.n - k - kb >= MXP_PANEL_MIN * p.nb;
+}
+// the first block whose inverses are formed after the factorisation
+static int64_t inv_first_after(const FactorPlan& p) {
+    const int64_t nblk = (p.n + p.nb - 1) / p.nb;
+    int64_t b = 0;
+    while (b < nblk && inverse_path(p, b * p.nb)) ++b;
+    return b;
+}
+
 template <int ST>
 static hipError_t prec_inverses(const FactorPlan& p, float* W, hipStream_t s) {
     const int64_t n = p.n, nb = p.nb;
     const int64_t nblk = (n + nb - 1) / nb;
-    dim3 g((unsigned)(nb / SR), (unsigned)nblk);
+    // blocks before blk0 got their inverses during the factorisation
+    const int64_t blk0 = inv_first_after(p);
+    dim3 g((unsigned)(nb / SR), (unsigned)(nblk - blk0));
     hipEvent_t pt = prof::begin(prof::DIAG, s);
-    k_inv_upper<<<g, 256, trsm_smem((int)nb), s>>>(n, (int)nb, p.Trm, p.uinv, p.uinv_full);
-    k_inv_lower<<<g, 256, trsm_smem((int)nb), s>>>(n, (int)nb, p.T, p.linv, p.linv_full);
+    if (blk0 < nblk) {
+        k_inv_upper<<<g, 256, trsm_smem((int)nb), s>>>(n, (int)nb, blk0, p.Trm, p.uinv, p.uinv_full);
+        k_inv_lower<<<g, 256, trsm_smem((int)nb), s>>>(n, (int)nb, blk0, p.T, p.linv, p.linv_full);
+    }
     double fl = 2.0 / 3.0 * (double)n * nb * nb;
     if (prec_block(nb) == 2 * nb && n > nb) {
         const int64_t npair = (n + 2 * nb - 1) / (2 * nb);
@@ -807,6 +872,43 @@ static void trsm_desc(const FactorPlan& p, int64_t k, TrsmOne& g, int wg_begin) 
     g.inv_sb = p.inv_sb + set * scset;
 }
 
+// The descriptor of block step k for the inverse-based strip solves; tr:
+// the output tile rows of the panel_trsm launch (panel_rows of the largest
+// nb it serves); wg0: the first work-group numbers of the three launches.
+// Blocks without a trailing part (the last) only get their inverses.
+static void panel_desc(const FactorPlan& p, int64_t k, int tr, PanelOne& g, const int wg0[3]) {
+    const int nb = (int)p.nb;
+    const int kb = (int)(p.n - k < nb ? p.n - k : nb);
+    const int64_t m = p.n - k - kb;
+    const int64_t blk = k / nb;
+    const int set = (int)(blk & 3);
+    const int eb = dtype_bytes(p.update);
+    const int64_t opset = p.op_rows * nb, scset = p.op_rows / 32;
+    const int64_t D = prec_block(nb), gsz = D / nb, o = (blk % gsz) * nb;
+    g.A = p.A; g.lda = p.lda; g.n = p.n; g.k = k; g.ldi = D;
+    g.nb = nb; g.kbp = (int)rup(kb, 64);
+    g.ntile = m > 0 ? (int)(rup(m, 256) / tr) : 0;
+    g.pad = g.pad2 = 0;
+    g.wg_inv = wg0[0] + 2 * (g.kbp / SR);
+    g.wg_split = wg0[1] + (m > 0 ? 2 * (nb / 16) : 0);
+    g.wg_trsm = wg0[2] + 2 * g.ntile;
+    g.T = p.T + blk * nb * nb;
+    g.Trm = p.Trm + blk * nb * nb;
+    g.linv = p.linv + blk * nb * 64;
+    g.uinv = p.uinv + blk * nb * 64;
+    g.Li = p.linv_full + (blk / gsz) * D * D + o + o * D;
+    g.Ui = p.uinv_full + (blk / gsz) * D * D + o + o * D;
+    g.ub = p.binv;
+    g.lb = (char*)p.binv + (size_t)3 * nb * nb * 2;
+    g.ubs = p.binv_sc;
+    g.lbs = p.binv_sc + nb;
+    g.Lq = (char*)p.Lq + (size_t)set * opset * eb;
+    g.inv_sa = p.inv_sa + set * scset;
+    g.lsc_blk = p.lsc + blk * ((p.n + SR - 1) / SR);
+    g.Uq = (char*)p.Uq + (size_t)set * opset * eb;
+    g.inv_sb = p.inv_sb + set * scset;
+}
+
 // The trailing updates of the block steps, taken in pairs: block column and
 // row k+1 receive the update of step k alone (they form panel k+1), and
 // everything beyond them the updates of steps k and k+1 in one pass with K =
@@ -885,6 +987,7 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
     hipError_t e;
     Lookahead* LA = la;
     ST_T* A = (ST_T*)p.A;
+    constexpr bool NP = ST == F16 || ST == BF16;     // strip solves through the block inverses
     const int64_t n = p.n, lda = p.lda;
     const int nb = (int)p.nb;
 
@@ -901,13 +1004,36 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
                                 p.dsync + blk * diag_sync_words(), p.info, st);
         if (e2) return e2;
         prof::end(pt, prof::DIAG, st, 2.0 / 3.0 * kb * (double)kb * kb, 2.0 * kb * (double)kb * sizeof(ST_T));
-        return hipGetLastError();
+        if ((e2 = hipGetLastError())) return e2;
+        if (NP && inverse_path(p, k)) {
+            // the block's inverses and their 16-bit parts (the strip products' B operands)
+            PanelGroup pg;
+            const int wg0[3] = {0, 0, 0};
+            panel_desc(p, k, panel_rows(ST, nb), pg.g[0], wg0);
+            pg.count = 1;
+            hipEvent_t pi = prof::begin(prof::TRSM, st);
+            if ((e2 = block_inverses(pg, pg.g[0].wg_inv, nb, st))) return e2;
+            if (pg.g[0].wg_split > 0 && (e2 = panel_split(ST, pg, pg.g[0].wg_split, nb, st))) return e2;
+            prof::end(pi, prof::TRSM, st, 4.0 / 3.0 * kb * (double)kb * kb, 8.0 * kb * (double)kb);
+        }
+        return hipSuccess;
     };
     // strip TRSMs of block k (wide grids: all CUs)
     auto trsm = [&](int64_t k, hipStream_t st) -> hipError_t {
         const int kb = (int)(n - k < nb ? n - k : nb);
         const int64_t m = n - k - kb;
         if (m <= 0) return hipSuccess;
+        if (NP && inverse_path(p, k)) {
+            PanelGroup pg;
+            const int wg0[3] = {0, 0, 0};
+            panel_desc(p, k, panel_rows(ST, nb), pg.g[0], wg0);
+            pg.count = 1;
+            hipEvent_t pt = prof::begin(prof::TRSM, st);
+            hipError_t e2 = panel_trsm(ST, OP, pg, pg.g[0].wg_trsm, nb, st);
+            prof::end(pt, prof::TRSM, st, 4.0 * m * (double)nb * nb,
+                      4.0 * m * (double)nb * sizeof(ST_T) + 2.0 * m * (double)nb * sizeof(OP_T));
+            return e2;
+        }
         TrsmGroup grp;
         trsm_desc<ST, OP>(p, k, grp.g[0], 0);
         grp.count = 1;
@@ -1024,6 +1150,7 @@ template <int ST, int OP>
 static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t s) {
     typedef typename Store<ST>::T ST_T;
     typedef typename Operand<OP>::T OP_T;
+    constexpr bool NP = ST == F16 || ST == BF16;     // strip solves through the block inverses
     hipError_t e;
     if ((e = hipFuncSetAttribute((const void*)k_trsm<ST, OP>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)trsm_smem(1024))))
@@ -1047,7 +1174,8 @@ static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t
     auto panels = [&](int64_t t) -> hipError_t {
         DiagCall dc[GEMM_GROUP_MAX];
         TrsmGroup tg;
-        int nd = 0, nt = 0, wg = 0, nbmax = 64;
+        PanelGroup pg;
+        int nd = 0, nt = 0, np = 0, wg = 0, nbmax = 64, pnbmax = 64;
         for (int g = 0; g < count; ++g) {
             const FactorPlan& p = P[g];
             const int nb = (int)p.nb;
@@ -1058,6 +1186,11 @@ static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t
             dc[nd++] = DiagCall{p.A, p.lda, k, kb, (int)rup(kb, 64), nb, p.T + blk * nb * nb, p.Trm + blk * nb * nb,
                                 p.linv + blk * nb * 64, p.uinv + blk * nb * 64, p.dsync + blk * diag_sync_words(),
                                 p.info};
+            if (NP && inverse_path(p, k)) {
+                pg.g[np++].nb = nb;                       // descriptors filled below (tile rows need nbmax)
+                pnbmax = nb > pnbmax ? nb : pnbmax;
+                continue;
+            }
             if (m <= 0) continue;
             trsm_desc<ST, OP>(p, k, tg.g[nt], wg);
             wg = tg.g[nt++].wg_end;
@@ -1065,7 +1198,26 @@ static hipError_t factor_group_typed(const FactorPlan* P, int count, hipStream_t
         }
         if (!nd) return hipSuccess;
         hipError_t e2 = diag_lu_group(ST, dc, nd, s);
-        if (e2 || !nt) return e2;
+        if (e2) return e2;
+        if (np) {
+            // the steps on the inverse path: inverses, their parts, the strip products
+            int wg0[3] = {0, 0, 0}, i = 0;
+            for (int g = 0; g < count; ++g) {
+                const FactorPlan& p = P[g];
+                const int64_t k = t * p.nb;
+                if (k >= p.n || !inverse_path(p, k)) continue;
+                panel_desc(p, k, panel_rows(ST, pnbmax), pg.g[i], wg0);
+                wg0[0] = pg.g[i].wg_inv; wg0[1] = pg.g[i].wg_split; wg0[2] = pg.g[i].wg_trsm;
+                ++i;
+            }
+            pg.count = np;
+            hipEvent_t pt = prof::begin(prof::TRSM, s);
+            if ((e2 = block_inverses(pg, wg0[0], pnbmax, s))) return e2;
+            if ((e2 = panel_split(ST, pg, wg0[1], pnbmax, s))) return e2;
+            if ((e2 = panel_trsm(ST, OP, pg, wg0[2], pnbmax, s))) return e2;
+            prof::end(pt, prof::TRSM, s, 0.0, 0.0);
+        }
+        if (!nt) return hipSuccess;
         tg.count = nt;
         hipEvent_t pt = prof::begin(prof::TRSM, s);
         k_trsm<ST, OP><<<wg, 256, trsm_smem(nbmax), s>>>(tg);
