@@ -1,7 +1,7 @@
 // diag.hip -- FP32 LU without pivoting of one diagonal block (the panel
-// factorisation of the right-looking blocked LU, Section 3 "HPL-MxP": the
-// diagonal block is factored in 32-bit arithmetic before the 16-bit
-// trailing update).
+// factorisation of the right-looking blocked LU; paper: "Algorithmic
+// Framework" and its Figure 1: the panel is factored in 32-bit arithmetic
+// before the 16-bit trailing update).
 //
 // The block is at most 1024 x 1024 and its factorisation is a chain of small
 // dependent steps over 32 x 32 tiles of an FP32 copy T (column-major, ld =
