@@ -39,7 +39,10 @@ __global__ __launch_bounds__(256) void k_scale_rows(int64_t n, const double* __r
 // chain always progresses; each wait is still bounded and on expiry sets
 // *err and lets the work-group exit.  All sums are taken in a fixed order
 // (deterministic results).
-constexpr int TS = 64;
+#ifndef MXP_TRSV_TS
+#define MXP_TRSV_TS 64
+#endif
+constexpr int TS = MXP_TRSV_TS;
 
 // Values exchanged between work-groups (block solutions, block right-hand
 // sides) are written and read with device-scope atomic accesses, which go to
@@ -116,7 +119,6 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
     constexpr int RPL = 16 / (int)sizeof(T);   // rows per lane: one 16-byte load
     constexpr int RG = TS / RPL;               // lanes per column
     constexpr int CPI = 64 / RG;               // columns per wave and load
-    static_assert(CPI >= 4, "part[][] also holds the four column groups of the diagonal apply");
     __shared__ double zs[1024];
     __shared__ double part[4][CPI][TS];
     __shared__ double w[TS];
@@ -243,7 +245,10 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
     const int rl0 = (int)(r0 - cj);
     const int clo = LOWER ? 0 : rl0, chi = LOWER ? (rl0 + TS < kbj ? rl0 + TS : kbj) : kbj;
     const int qv = (chi - clo + 3) / 4, cbv = clo + wv * qv, cev = (cbv + qv < chi) ? cbv + qv : chi;
-    const int rsub = lane % 16, csub = lane / 16;
+    // a lane: four consecutive rows (RQ row quads cover the strip), one of CS column groups
+    constexpr int RQ = TS / 4, CS = 64 / RQ;
+    static_assert(CPI >= CS, "part[][] also holds the column groups of the diagonal apply");
+    const int rsub = lane % RQ, csub = lane / RQ;
     const float* colbase = inv_all + j * (int64_t)db * db + rl0 + 4 * rsub;
     // this strip's rows of the block right-hand side are final
     if (tid < rows) put_shared(tbuf + r0 + tid, w[tid]);
@@ -257,7 +262,7 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
     float4 iv0[NIV];
 #pragma unroll
     for (int t = 0; t < NIV; ++t) {
-        const int c = cbv + csub + 4 * t;
+        const int c = cbv + csub + CS * t;
         iv0[t] = *(const float4*)(colbase + (int64_t)(c < cev ? c : clo) * db);
     }
     if (!wait_flag(&cnt[j], strips_of(j), err, &s_abort)) return;
@@ -276,22 +281,22 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
         };
 #pragma unroll
         for (int t = 0; t < NIV; ++t) {
-            const int c = cb + csub + 4 * t;
+            const int c = cb + csub + CS * t;
             fma4(iv0[t], c < ce ? zs[c] : 0.0);
         }
         // the rest in batches of NIV loads in flight at once, without
         // conditions (a column past the range reads column clo and is
         // weighted zero)
-        for (int c0b = cb + csub + 4 * NIV; c0b < ce; c0b += 4 * NIV) {
+        for (int c0b = cb + csub + CS * NIV; c0b < ce; c0b += CS * NIV) {
             float4 iv[NIV];
 #pragma unroll
             for (int t = 0; t < NIV; ++t) {
-                const int c = c0b + 4 * t;
+                const int c = c0b + CS * t;
                 iv[t] = *(const float4*)(colbase + (int64_t)(c < ce ? c : clo) * db);
             }
 #pragma unroll
             for (int t = 0; t < NIV; ++t) {
-                const int c = c0b + 4 * t;
+                const int c = c0b + CS * t;
                 fma4(iv[t], c < ce ? zs[c] : 0.0);
             }
         }
@@ -302,7 +307,7 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
     if (tid < rows) {
         double t = 0.0;
         for (int u = 0; u < 4; ++u)
-            for (int v2 = 0; v2 < 4; ++v2) t += part[u][v2][tid];
+            for (int v2 = 0; v2 < CS; ++v2) t += part[u][v2][tid];
         put_shared(out + r0 + tid, t);
     }
     signal_flag(&ready[j]);
