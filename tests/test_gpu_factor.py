@@ -152,6 +152,11 @@ def _backward_bound(A, L, U, nb, update, store):
 
 CASES = [(1000, 128, p[0], p[1]) for p in PAIRS] + [(4096, 512, "f16", "f16"), (4096, 512, "bf16", "bf16"),
                                                     (4096, 512, "f8", "f16"), (1100, 256, "f8", "bf16")]
+# block steps whose trailing part is at least 16 blocks solve their strips
+# through the diagonal block's inverses (16-bit storage): these sizes take
+# that path for their first blocks (FP16 with 64-row tiles and two idle
+# waves at nb = 64, BF16 and FP8 operands with 32-row tiles)
+CASES += [(2048, 64, "f16", "f16"), (2600, 128, "bf16", "bf16"), (2600, 128, "f8", "f16"), (2400, 128, "f8", "bf16")]
 
 
 @pytest.mark.parametrize("n,nb,update,store", CASES)

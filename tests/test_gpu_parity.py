@@ -141,6 +141,9 @@ CASES = [
     (64, 64, "f16", "f16"),
     (65, 64, "f32", "f32"),
     (1, 64, "f32", "f32"),
+    # the first blocks' strips through the diagonal blocks' inverses
+    (2100, 64, "f16", "f16"),
+    (2400, 128, "bf16", "bf16"),
 ]
 
 
