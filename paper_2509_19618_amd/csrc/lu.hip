@@ -960,13 +960,13 @@ static int cross_calls(const FactorPlan& p, int64_t j, bool pair, int64_t b, Gem
 
 // Right-looking blocked LU with look-ahead, the updates taken in pairs (see
 // above).  With the pair (k, k1), k1 = k + nb, and k2, k3 the next two
-// blocks, the caller's stream runs the pair's update in three parts -- the
+// blocks, the caller's stream runs the pair's update in two launches -- the
 // rest of block column and row k2 (the diagonal block k2 is updated on the
-// side stream), block column and row k3, everything beyond -- while the side
-// stream runs the chain that sets the pace of the late steps: the diagonal
-// block k2, its LU, the strip TRSMs of step k2 (after the first part), the
-// update of block column and row k3 by step k2 alone (after the second), the
-// LU and TRSMs of block k3.  One event per hand-over; in the late steps each
+// side stream) with block column and row k3, then everything beyond -- while
+// the side stream runs the chain that sets the pace of the late steps: the
+// diagonal block k2, its LU, the strip TRSMs of step k2 and the update of
+// block column and row k3 by step k2 alone (after the first launch), the LU
+// and TRSMs of block k3.  One event per hand-over; in the late steps each
 // has fired before its wait is reached.  The operand sets of the pair are
 // rewritten by the TRSMs two pairs later, which the side stream enqueues
 // after it has seen the pair's last update end.
@@ -1099,18 +1099,23 @@ static hipError_t factor_typed(const FactorPlan& p, hipStream_t s, Lookahead* la
         if ((e = hipStreamWaitEvent(LA->side, LA->ev_upd, 0))) return e;
         if ((e = square(k, k2, w2, LA->side))) return e;
         if ((e = diag(k2, LA->side))) return e;
-        // main: the rest of block column and row k2 (needs panel k1)
+        // main: the rest of block column and row k2 (needs panel k1) and
+        // block column and row k3, in one launch (the side stream's diagonal
+        // LU of k2 outlasts both), then everything beyond
         if (side_used && (e = hipStreamWaitEvent(s, LA->ev_panel, 0))) return e;
-        if (n - k2 - w2 > 0) {
-            GemmCall c[2] = {pair_call<ST, OP>(p, k, true, k2 + w2, k2, n - k2 - w2, w2),
-                             pair_call<ST, OP>(p, k, true, k2, k2 + w2, w2, n - k2 - w2)};
-            if ((e = gemm(c, 2, s))) return e;
+        {
+            GemmCall c[4];
+            int cnt = 0;
+            if (n - k2 - w2 > 0) {
+                c[cnt++] = pair_call<ST, OP>(p, k, true, k2 + w2, k2, n - k2 - w2, w2);
+                c[cnt++] = pair_call<ST, OP>(p, k, true, k2, k2 + w2, w2, n - k2 - w2);
+            }
+            if (k3 < n) cnt += cross_calls<ST, OP>(p, k, true, k3, c + cnt);
+            if (cnt && (e = gemm(c, cnt, s))) return e;
         }
         if ((e = hipEventRecord(LA->ev_cross, s))) return e;
         if (k3 < n) {
             const int64_t w3 = n - k3 < nb ? n - k3 : nb;
-            // main: block column and row k3, then everything beyond
-            if ((e = cross(k, true, k3, s))) return e;
             if ((e = hipEventRecord(LA->ev_next, s))) return e;
             if (n - k3 - w3 > 0) {
                 GemmCall c = pair_call<ST, OP>(p, k, true, k3 + w3, k3 + w3, n - k3 - w3, n - k3 - w3);

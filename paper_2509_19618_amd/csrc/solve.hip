@@ -120,7 +120,8 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
     constexpr int RG = TS / RPL;               // lanes per column
     constexpr int CPI = 64 / RG;               // columns per wave and load
     __shared__ double zs[1024];
-    __shared__ double part[4][CPI][TS];
+    constexpr int PCOLS = CPI > 64 / (TS / 8) ? CPI : 64 / (TS / 8);   // column groups: panels, diagonal apply
+    __shared__ double part[4][PCOLS][TS];
     __shared__ double w[TS];
     __shared__ int s_abort;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -235,21 +236,38 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
             i += istep;
         }
     }
-    // this strip's rows of the diagonal-block inverse (lower / upper
-    // triangular: only the columns up to / from the strip's rows), four rows
-    // per lane with 16-byte loads, the waves splitting the columns.  They do
-    // not depend on the other strips: the first batch is loaded while the
-    // strips of the block meet.
+    // The block's rows of its diagonal-block inverse (lower / upper
+    // triangular: a row takes the columns up to / from itself), applied in
+    // half strips of HS rows: work-group s of the block takes half strip s and
+    // its mirror 2 nst - 1 - s, so that every work-group gets the same share
+    // of the triangle (by whole strips the last strip of a lower block holds
+    // sixteen times the first's columns, and the step waits for it).  A lane:
+    // four consecutive rows (16-byte loads), one of CS column groups; the waves
+    // split a half strip's columns.  The first batch of loads is issued while
+    // the strips of the block meet.
     const int64_t cj = j * db;
     const int kbj = (int)(n - cj < db ? n - cj : db);
-    const int rl0 = (int)(r0 - cj);
-    const int clo = LOWER ? 0 : rl0, chi = LOWER ? (rl0 + TS < kbj ? rl0 + TS : kbj) : kbj;
-    const int qv = (chi - clo + 3) / 4, cbv = clo + wv * qv, cev = (cbv + qv < chi) ? cbv + qv : chi;
-    // a lane: four consecutive rows (RQ row quads cover the strip), one of CS column groups
-    constexpr int RQ = TS / 4, CS = 64 / RQ;
-    static_assert(CPI >= CS, "part[][] also holds the column groups of the diagonal apply");
+    const int nst = (int)strips_of(j);
+    const int s_in = (int)((r0 - cj) / TS);
+    constexpr int HS = TS / 2, RQ = HS / 4, CS = 64 / RQ;
+    static_assert(PCOLS >= CS, "part[][] also holds the column groups of the diagonal apply");
     const int rsub = lane % RQ, csub = lane / RQ;
-    const float* colbase = inv_all + j * (int64_t)db * db + rl0 + 4 * rsub;
+    const float* blkinv = inv_all + j * (int64_t)db * db + 4 * rsub;
+    struct Half {
+        int r0, rows, clo, cb, ce;
+    };
+    auto half = [&](int h) {
+        Half H;
+        H.r0 = HS * h;
+        H.rows = kbj - H.r0 < HS ? kbj - H.r0 : HS;               // <= 0: nothing to do
+        H.clo = LOWER ? 0 : H.r0;
+        const int chi = LOWER ? (H.r0 + HS < kbj ? H.r0 + HS : kbj) : kbj;
+        const int q = chi > H.clo ? (chi - H.clo + 3) / 4 : 0;
+        H.cb = H.clo + wv * q;
+        H.ce = H.cb + q < chi ? H.cb + q : chi;
+        return H;
+    };
+    const Half HA = half(s_in), HB = half(2 * nst - 1 - s_in);
     // this strip's rows of the block right-hand side are final
     if (tid < rows) put_shared(tbuf + r0 + tid, w[tid]);
     signal_flag(&cnt[j]);
@@ -260,18 +278,24 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
 #endif
     constexpr int NIV = MXP_TRSV_NIV;     // inverse loads in flight per lane (16 bytes each)
     float4 iv0[NIV];
+    {
+        const float* rb = blkinv + HA.r0;
 #pragma unroll
-    for (int t = 0; t < NIV; ++t) {
-        const int c = cbv + csub + CS * t;
-        iv0[t] = *(const float4*)(colbase + (int64_t)(c < cev ? c : clo) * db);
+        for (int t = 0; t < NIV; ++t) {
+            const int c = HA.cb + csub + CS * t;
+            iv0[t] = *(const float4*)(rb + (int64_t)(c < HA.ce ? c : HA.clo) * db);
+        }
     }
     if (!wait_flag(&cnt[j], strips_of(j), err, &s_abort)) return;
 #pragma unroll
     for (int t = 0; t < NIV; ++t) pin4f(iv0[t]);
     for (int c = tid; c < kbj; c += 256) zs[c] = get_shared(tbuf + cj + c);
     __syncthreads();
-    {
-        const int cb = cbv, ce = cev;
+    // one half strip: its columns in batches of NIV loads in flight at once,
+    // without conditions (a column past the range reads column clo and is
+    // weighted zero); the first batch is given (pre) or loaded here
+    auto apply = [&](const Half& H, float4 (&pre)[NIV], bool has_pre) {
+        const float* rb = blkinv + H.r0;
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         auto fma4 = [&](const float4 v, double zc) {
             acc[0] += (double)v.x * zc;
@@ -279,37 +303,41 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
             acc[2] += (double)v.z * zc;
             acc[3] += (double)v.w * zc;
         };
+        int c0b = H.cb + csub;
+        if (has_pre) {
 #pragma unroll
-        for (int t = 0; t < NIV; ++t) {
-            const int c = cb + csub + CS * t;
-            fma4(iv0[t], c < ce ? zs[c] : 0.0);
+            for (int t = 0; t < NIV; ++t) {
+                const int c = c0b + CS * t;
+                fma4(pre[t], c < H.ce ? zs[c] : 0.0);
+            }
+            c0b += CS * NIV;
         }
-        // the rest in batches of NIV loads in flight at once, without
-        // conditions (a column past the range reads column clo and is
-        // weighted zero)
-        for (int c0b = cb + csub + CS * NIV; c0b < ce; c0b += CS * NIV) {
+        for (; c0b < H.ce; c0b += CS * NIV) {
             float4 iv[NIV];
 #pragma unroll
             for (int t = 0; t < NIV; ++t) {
                 const int c = c0b + CS * t;
-                iv[t] = *(const float4*)(colbase + (int64_t)(c < ce ? c : clo) * db);
+                iv[t] = *(const float4*)(rb + (int64_t)(c < H.ce ? c : H.clo) * db);
             }
 #pragma unroll
             for (int t = 0; t < NIV; ++t) {
                 const int c = c0b + CS * t;
-                fma4(iv[t], c < ce ? zs[c] : 0.0);
+                fma4(iv[t], c < H.ce ? zs[c] : 0.0);
             }
         }
 #pragma unroll
         for (int k = 0; k < 4; ++k) part[wv][csub][4 * rsub + k] = acc[k];
-    }
-    __syncthreads();
-    if (tid < rows) {
-        double t = 0.0;
-        for (int u = 0; u < 4; ++u)
-            for (int v2 = 0; v2 < CS; ++v2) t += part[u][v2][tid];
-        put_shared(out + r0 + tid, t);
-    }
+        __syncthreads();
+        if (tid < H.rows) {
+            double t = 0.0;
+            for (int u = 0; u < 4; ++u)
+                for (int v2 = 0; v2 < CS; ++v2) t += part[u][v2][tid];
+            put_shared(out + cj + H.r0 + tid, t);
+        }
+        __syncthreads();                      // part[] free for the next half
+    };
+    if (HA.rows > 0) apply(HA, iv0, true);
+    if (HB.rows > 0) apply(HB, iv0, false);
     signal_flag(&ready[j]);
 }
 
