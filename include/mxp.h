@@ -121,8 +121,11 @@ int mxp_generate(int64_t n, int64_t nrhs, uint64_t seed, int kind, double gamma,
  * Factorisation -- "Algorithmic Framework", Figure 1.
  * Right-looking blocked LU without pivoting with block size nb.  Per block
  * step: the diagonal block is factored in FP32; the block column
- * L21 = A21 U11^-1 and block row U12 = L11^-1 A12 are formed in FP32 by
- * blocked substitution; both are rounded to the update format `update`
+ * L21 = A21 U11^-1 and block row U12 = L11^-1 A12 are formed at FP32
+ * quality -- while the trailing part spans at least 16 blocks and `store`
+ * is 16-bit, as products with the diagonal block's FP32 inverses split into
+ * 16-bit parts (matrix cores, FP32 accumulation), otherwise by blocked FP32
+ * substitution; both are rounded to the update format `update`
  * (MXP_F16, MXP_BF16, MXP_F8E4M3 with a power-of-two scale per strip of
  * rows of L21 / columns of U12; MXP_F32 for an all-FP32 factorisation);
  * the trailing matrix is updated A22 <- A22 - L21 U12 on the matrix cores
@@ -173,7 +176,8 @@ int mxp_factor(int64_t n, int64_t nb, int update, int store, int scaling, const 
  * mxp_factor_group -- the factorisations of up to 8 independent matrices of
  * the same formats in lockstep on one stream (the batched launches of the
  * solve server; not in the paper): per block step ONE launch factors the
- * diagonal blocks of all of them, ONE launch forms all their strip TRSMs,
+ * diagonal blocks of all of them, ONE launch forms all their strip solves
+ * (one launch per kernel of the inverse-based form),
  * and per pair of block steps ONE launch updates all their next block
  * columns and rows and ONE all their trailing matrices (the two steps
  * merged, as in mxp_factor), each kernel finding its matrix through a
