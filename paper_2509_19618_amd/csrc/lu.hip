@@ -5,7 +5,7 @@
 // the input allowed).
 //
 // Per block step k (block size nb):
-//   1. diagonal block A11 -> FP32, LU in FP32 by up to sixteen cooperating
+//   1. diagonal block A11 -> FP32, LU in FP32 by up to 24 cooperating
 //      work-groups over 32x32 tiles (diag.hip); inverses of the 64x64
 //      diagonal sub-blocks of L11 and U11 kept;
 //   2. L21 = A21 U11^-1 and U12 = L11^-1 A12 by blocked substitution in
