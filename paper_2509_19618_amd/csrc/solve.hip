@@ -26,19 +26,30 @@ __global__ __launch_bounds__(256) void k_scale_rows(int64_t n, const double* __r
 }
 
 // ---------------------------------------------------------------- block substitution
-// One kernel per triangular solve, every right-hand side at once (one row of
-// work-groups per right-hand side, each with its own flags).  Work-group = one
-// strip of TS rows; strips are processed as a dataflow: a strip of block j accumulates the products of
-// its rows of the off-diagonal factor with every dependency block's solution
-// as soon as that block is published (flag `ready`), then the strips of block
-// j meet (flag `cnt`) and each applies its rows of the FP32 inverse of the
-// diagonal block and publishes them.  Forward (L): dependencies are the blocks
-// before j, strips run in increasing order; backward (U): the blocks after j,
-// strips in decreasing order.  Work-groups are dispatched in index order and
-// every wait is on a strip of smaller index (or of the same block), so the
-// chain always progresses; each wait is still bounded and on expiry sets
-// *err and lets the work-group exit.  All sums are taken in a fixed order
-// (deterministic results).
+// One kernel per triangular solve, every right-hand side at once (each
+// right-hand side with its own flags).  Work-group = one strip of TS rows;
+// strips are processed as a dataflow: a strip of block j accumulates the
+// products of its rows of the off-diagonal factor with every dependency
+// block's solution as soon as that block is published (flag `ready`),
+// publishes its rows of the block right-hand side (its strip flag), and
+// applies its rows of the FP32 inverse of the diagonal block once the strips
+// those rows depend on have published theirs (the inverse is triangular:
+// the strips above it in the block for L, below it for U); it then counts
+// itself into the block's `ready`.  Forward (L): dependencies are the blocks
+// before j, strips run in increasing order; backward (U): the blocks after
+// j, strips in decreasing order.
+//
+// A work-group takes its position (right-hand side, strip) from a counter
+// of the launch when it starts, not from its index, and every wait is on
+// strips of earlier positions, so every wait is on work-groups that have
+// started: the earliest unfinished one waits on none and runs to its end.
+// The launch then always drains, whatever else holds the device: the
+// hardware deals the indices out to the XCDs, each dispatching its share in
+// order, and with other launches on other streams it can hold back a
+// launch's remaining work-groups while that launch's resident ones spin.
+// Each wait is still bounded and on expiry sets *err and lets the
+// work-group exit.  All sums are taken in a fixed order (deterministic
+// results).
 #ifndef MXP_TRSV_TS
 #define MXP_TRSV_TS 64
 #endif
@@ -97,6 +108,30 @@ __device__ bool wait_flag(const unsigned* flag, unsigned target, int* err, int* 
     return !*s_abort;
 }
 
+// bounded wait, by the first wave, until the cnt flags f[0 .. cnt) are all
+// raised (cnt <= 64: one lane per flag)
+__device__ bool wait_all(const unsigned* f, int cnt, int* err, int* s_abort) {
+    if (threadIdx.x < 64) {
+        const int l = threadIdx.x;
+        int ok = 1;
+        unsigned it = 0;
+        for (;;) {
+            const bool up = l >= cnt || __hip_atomic_load(f + l, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            if (__all(up)) break;
+            if (++it > (1u << 24) || __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                ok = 0;
+                if (l == 0) atomicOr(err, 1);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        if (ok) sync_acquire();
+        if (l == 0) *s_abort = !ok;
+    }
+    __syncthreads();
+    return !*s_abort;
+}
+
 // every wave's stores are released at agent scope and precede the barrier;
 // the flag then counts one more strip with release semantics
 __device__ void signal_flag(unsigned* flag) {
@@ -114,7 +149,8 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
                                               const float* __restrict__ lsc, int64_t nstrips32,
                                               const double* __restrict__ rhs, int64_t ld_rhs,
                                               double* __restrict__ tbuf, double* __restrict__ out, int64_t ld_out,
-                                              unsigned* flags, int64_t flag_stride, int* err) {
+                                              unsigned* flags, int64_t flag_stride, unsigned* ticket,
+                                              int* err) {
     typedef typename Store<ST>::T T;
     constexpr int RPL = 16 / (int)sizeof(T);   // rows per lane: one 16-byte load
     constexpr int RG = TS / RPL;               // lanes per column
@@ -124,23 +160,29 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
     __shared__ double part[4][PCOLS][TS];
     __shared__ double w[TS];
     __shared__ int s_abort;
+    __shared__ unsigned s_pos;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-    // right-hand side blockIdx.y: its own vectors, block buffer and flags
-    rhs += blockIdx.y * ld_rhs;
-    out += blockIdx.y * ld_out;
-    tbuf += blockIdx.y * n;
-    flags += blockIdx.y * flag_stride;
+    // position in start order: strip pos % S of right-hand side pos / S (the
+    // grid is S x nrhs work-groups)
+    if (tid == 0) s_pos = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t S = (n + TS - 1) / TS, J = (n + nb - 1) / nb, gb = db / nb;
+    const int64_t pos = s_pos, px = pos % S, py = pos / S;
+    // right-hand side py: its own vectors, block buffer and flags
+    rhs += py * ld_rhs;
+    out += py * ld_out;
+    tbuf += py * n;
+    flags += py * flag_stride;
     // the substitution's diagonal blocks (size db, a multiple of nb: gb factor
     // blocks each) are the dataflow's steps; the off-diagonal products go by
     // factor block (each with its own strip factors)
-    const int64_t S = (n + TS - 1) / TS, J = (n + nb - 1) / nb, gb = db / nb;
-    const int64_t sidx = LOWER ? (int64_t)blockIdx.x : S - 1 - (int64_t)blockIdx.x;
+    const int64_t sidx = LOWER ? px : S - 1 - px;
     const int64_t j = sidx / (db / TS);
     const int64_t first = j * gb, last = (first + gb < J ? first + gb : J) - 1;
     const int64_t r0 = sidx * TS;
     const int rows = (int)(n - r0 < TS ? n - r0 : TS);
-    unsigned* cnt = flags;
-    unsigned* ready = flags + J;
+    unsigned* sflag = flags;          // one per strip: its rows of the block right-hand side are published
+    unsigned* ready = flags + S;      // one per block: strips that have published their solution rows
     auto strips_of = [&](int64_t b) -> unsigned {
         const int64_t kb = n - b * db < db ? n - b * db : db;
         return (unsigned)((kb + TS - 1) / TS);
@@ -236,15 +278,11 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
             i += istep;
         }
     }
-    // The block's rows of its diagonal-block inverse (lower / upper
-    // triangular: a row takes the columns up to / from itself), applied in
-    // half strips of HS rows: work-group s of the block takes half strip s and
-    // its mirror 2 nst - 1 - s, so that every work-group gets the same share
-    // of the triangle (by whole strips the last strip of a lower block holds
-    // sixteen times the first's columns, and the step waits for it).  A lane:
-    // four consecutive rows (16-byte loads), one of CS column groups; the waves
-    // split a half strip's columns.  The first batch of loads is issued while
-    // the strips of the block meet.
+    // The strip's rows of its diagonal-block inverse (lower / upper
+    // triangular: a row takes the columns up to / from itself), applied in two
+    // half strips of HS rows.  A lane: four consecutive rows (16-byte loads),
+    // one of CS column groups; the waves split a half strip's columns.  The
+    // first batch of loads is issued while the strips it depends on publish.
     const int64_t cj = j * db;
     const int kbj = (int)(n - cj < db ? n - cj : db);
     const int nst = (int)strips_of(j);
@@ -267,10 +305,10 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
         H.ce = H.cb + q < chi ? H.cb + q : chi;
         return H;
     };
-    const Half HA = half(s_in), HB = half(2 * nst - 1 - s_in);
+    const Half HA = half(2 * s_in), HB = half(2 * s_in + 1);
     // this strip's rows of the block right-hand side are final
     if (tid < rows) put_shared(tbuf + r0 + tid, w[tid]);
-    signal_flag(&cnt[j]);
+    signal_flag(&sflag[sidx]);
     // (issued after the signal, whose wait for this wave's stores would also
     // wait for them)
 #ifndef MXP_TRSV_NIV
@@ -286,10 +324,18 @@ __global__ __launch_bounds__(256) void k_trsv(int64_t n, int nb, int db, const t
             iv0[t] = *(const float4*)(rb + (int64_t)(c < HA.ce ? c : HA.clo) * db);
         }
     }
-    if (!wait_flag(&cnt[j], strips_of(j), err, &s_abort)) return;
+    // the strips whose right-hand side rows this strip's rows take: those
+    // above it in the block (L), below it (U)
+    const int64_t sb = sidx - s_in;
+    if (!(LOWER ? wait_all(sflag + sb, s_in, err, &s_abort)
+                : wait_all(sflag + sidx + 1, nst - 1 - s_in, err, &s_abort)))
+        return;
 #pragma unroll
     for (int t = 0; t < NIV; ++t) pin4f(iv0[t]);
-    for (int c = tid; c < kbj; c += 256) zs[c] = get_shared(tbuf + cj + c);
+    {
+        const int zlo = LOWER ? 0 : s_in * TS, zhi = LOWER ? s_in * TS + rows : kbj;
+        for (int c = zlo + tid; c < zhi; c += 256) zs[c] = get_shared(tbuf + cj + c);
+    }
     __syncthreads();
     // one half strip: its columns in batches of NIV loads in flight at once,
     // without conditions (a column past the range reads column clo and is
@@ -346,9 +392,14 @@ __global__ void k_zero_u32(unsigned* p, int64_t count) {
     if (i < count) p[i] = 0u;
 }
 
-// flag words of one right-hand side: cnt and ready of both solves (at most
-// ceil(n / 64) blocks each)
-static int64_t trsv_flag_words(int64_t n) { return 4 * (n / 64 + 2); }
+// flag words of one right-hand side: the strip flags (S = ceil(n / TS)) and
+// block flags (J = ceil(n / nb), nb >= 64) of both solves; those of the
+// first right-hand side also hold the two solves' start-order counters
+// (words 2 (S + J) and 2 (S + J) + 1)
+static int64_t trsv_flag_words(int64_t n) {
+    constexpr int64_t u = TS < 64 ? TS : 64;
+    return 4 * (n / u + 2);
+}
 
 size_t prec_work_bytes(int64_t n, int nr) {
     // S V, forward solution, block right-hand sides (n x nr each), flags, error word
@@ -391,10 +442,11 @@ static hipError_t prec_typed(const PrecPlan& p, const double* V, int64_t ldv, do
     const int db = (int)prec_block(nb);
     k_trsv<ST, true><<<dim3((unsigned)S, (unsigned)nr), 256, 0, s>>>(n, (int)nb, db, (const T*)p.A, p.lda, vec,
                                                                      p.linv_full, p.lsc, nstrips32, R, n, Tb, Y, n,
-                                                                     flags, fw, err);
+                                                                     flags, fw, flags + 2 * (S + J), err);
     k_trsv<ST, false><<<dim3((unsigned)S, (unsigned)nr), 256, 0, s>>>(n, (int)nb, db, (const T*)p.A, p.lda, vec,
                                                                       p.uinv_full, nullptr, nstrips32, Y, n, Tb, Z,
-                                                                      ldz, flags + 2 * J, fw, err);
+                                                                      ldz, flags + S + J, fw, flags + 2 * (S + J) + 1,
+                                                                      err);
     prof::end(pt, prof::PREC, s, 2.0 * n * (double)n * nr, (double)n * n * sizeof(T) + 8.0 * n * nb);
     return hipGetLastError();
 }

@@ -272,3 +272,42 @@ def test_concurrent_factorisations_from_two_threads():
         A, Bo, Xo, _ = oracle.solve(n, seed)
         x = res.X[0].cpu().numpy()
         assert np.abs(x - Xo[:, 0]).max() <= 1e-12 * np.abs(Xo[:, 0]).max()
+
+
+def test_concurrent_substitutions_from_several_threads():
+    # the preconditioner's dataflow kernels of three solves running at once
+    # on their own streams, each launch with more work-groups than fit on
+    # the device together: every apply completes (a wait that expired would
+    # raise) and equals the same apply run alone, bit for bit
+    print("three threads applying the preconditioner", flush=True)
+    cases = [(16384, 512, "bf16", 8, 31), (12288, 512, "f16", 8, 32), (9000, 512, "bf16", 5, 33)]
+    facs = {}
+    for n, nb, up, nrhs, seed in cases:
+        prob = mxp.mxp_generate(n, nrhs, seed, store=up)
+        fac = mxp.mxp_factor(prob, nb, up)
+        assert fac.info == 0
+        V = prob.B.clone()
+        facs[seed] = (fac, V, mxp.mxp_apply_prec(fac, V))
+    torch.cuda.synchronize()
+    bad = {}
+
+    def run(seed):
+        fac, V, Zref = facs[seed]
+        s = torch.cuda.Stream()
+        try:
+            with torch.cuda.stream(s):
+                for _ in range(10):
+                    Z = mxp.mxp_apply_prec(fac, V, stream=s)
+                    s.synchronize()
+                    if not torch.equal(Z, Zref):
+                        bad[seed] = "result differs from the apply run alone"
+                        return
+        except Exception as e:          # an expired wait raises MxpError
+            bad[seed] = repr(e)
+
+    ths = [threading.Thread(target=run, args=(c[-1],)) for c in cases]
+    for t in ths:
+        t.start()
+    for t in ths:
+        t.join()
+    assert not bad, bad
