@@ -359,7 +359,8 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(const DiagGroup grp) {
 #pragma unroll
         for (int c = 0; c < 32; ++c) X[c] = (c == lro) ? 1.0f : 0.0f;
         // by rows: X[i] = e_i - sum_{s<i} L[i][s] X[s]; row s of X is zero
-        // right of s, so the sweep stops at C1
+        // right of s, so the sweep stops at C1 (the steps unrolled, their
+        // sweeps by blocks of eight columns)
         auto linv_step = [&](int s2, auto C1) {
             constexpr int c1 = decltype(C1)::value;
             const int lr = opaque(lane & 31);
@@ -375,14 +376,13 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(const DiagGroup grp) {
                 for (int c = 0; c < c1; ++c) X[c] = fmaf(-l, pv[c], X[c]);
             }
         };
-#pragma unroll 1
-        for (int s2 = 0; s2 < 8; ++s2) linv_step(s2, std::integral_constant<int, 8>());
-#pragma unroll 1
-        for (int s2 = 8; s2 < 16; ++s2) linv_step(s2, std::integral_constant<int, 16>());
-#pragma unroll 1
-        for (int s2 = 16; s2 < 24; ++s2) linv_step(s2, std::integral_constant<int, 24>());
-#pragma unroll 1
-        for (int s2 = 24; s2 < 31; ++s2) linv_step(s2, std::integral_constant<int, 32>());
+#pragma unroll
+        for (int s2 = 0; s2 < 31; ++s2) {
+            if (s2 < 8) linv_step(s2, std::integral_constant<int, 8>());
+            else if (s2 < 16) linv_step(s2, std::integral_constant<int, 16>());
+            else if (s2 < 24) linv_step(s2, std::integral_constant<int, 24>());
+            else linv_step(s2, std::integral_constant<int, 32>());
+        }
         const int o = 32 * (t & 1);
         float* L64 = linv + (t >> 1) * 4096;
         if (lh == 0) {
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(const DiagGroup grp) {
     auto tile_uinv = [&](int t) {
         stage_cm(sA, Tt(t, t), ldt, lr, lh);
         lds_order();
-        v32f x;   // read at the step index (s_set_gpr_idx)
+        v32f x;
         float X[32];
         const int lro = opaque(lr);
 #pragma unroll
@@ -409,7 +409,8 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(const DiagGroup grp) {
         }
         const float dinv = __builtin_amdgcn_rcpf(sA[lro * TP + lro]);   // 1 / U[lr][lr], as in the leaf
         // by rows, last row first: X[i] = (e_i - sum_{s>i} U[i][s] X[s]) / U[i][i];
-        // row s of X is zero left of s, so the sweep starts at C0
+        // row s of X is zero left of s, so the sweep starts at C0 (the steps
+        // unrolled, their sweeps by blocks of eight columns)
         auto uinv_step = [&](int s2, auto C0) {
             const int lr = opaque(lane & 31);
             const float sc = (lr == s2) ? dinv : 1.0f;
@@ -425,14 +426,13 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(const DiagGroup grp) {
                 for (int c = decltype(C0)::value; c < 32; ++c) X[c] = fmaf(-w, pv[c], X[c]);
             }
         };
-#pragma unroll 1
-        for (int s2 = 31; s2 >= 24; --s2) uinv_step(s2, std::integral_constant<int, 24>());
-#pragma unroll 1
-        for (int s2 = 23; s2 >= 16; --s2) uinv_step(s2, std::integral_constant<int, 16>());
-#pragma unroll 1
-        for (int s2 = 15; s2 >= 8; --s2) uinv_step(s2, std::integral_constant<int, 8>());
-#pragma unroll 1
-        for (int s2 = 7; s2 >= 0; --s2) uinv_step(s2, std::integral_constant<int, 0>());
+#pragma unroll
+        for (int s2 = 31; s2 >= 0; --s2) {
+            if (s2 >= 24) uinv_step(s2, std::integral_constant<int, 24>());
+            else if (s2 >= 16) uinv_step(s2, std::integral_constant<int, 16>());
+            else if (s2 >= 8) uinv_step(s2, std::integral_constant<int, 8>());
+            else uinv_step(s2, std::integral_constant<int, 0>());
+        }
         lds_order();
         if (lh == 0) {
 #pragma unroll
