@@ -78,6 +78,8 @@ def lib():
             "orc_residual_rows": (None, [i64, u64, ci, dbl, P, P, P, i64, P]),
             "orc_hpl_eta_regen": (dbl, [i64, u64, ci, dbl, P, P, dbl]),
             "orc_jacobi_regen": (i64, [i64, u64, ci, dbl, P, P, i64, dbl]),
+            "orc_diag_all": (None, [i64, u64, ci, dbl, P]),
+            "orc_jacobi_sweep_regen": (dbl, [i64, u64, ci, dbl, P, P, P]),
             "orc_gmres_cycle": (i64, [i64, P, i64, P, i64, P, P, i64, dbl, P, i64, P, P, P, P]),
             "orc_gmres_ir": (ctypes.c_int, [i64, P, i64, P, i64, P, P, i64, i64, dbl, dbl, P, P, P]),
             "orc_round_fmt": (dbl, [ctypes.c_int, dbl, ctypes.c_int]),
@@ -206,10 +208,25 @@ def hpl_eta_regen(n: int, seed: int, x, b, kind: int = GEN_DOMINANT, gamma: floa
 
 
 def jacobi_regen(n: int, seed: int, b, max_sweeps: int = 200, tol: float = 2.0 ** -50, kind: int = GEN_DOMINANT,
-                 gamma: float = 0.0):
+                 gamma: float = 0.0, progress=None):
+    """Jacobi from x = 0 with A regenerated (orc_jacobi_regen).  With progress
+    (a callable taking the sweep count and the sweep's largest change) the
+    sweeps are run one call at a time -- the same arithmetic in the same
+    order -- and reported as they finish."""
     x = np.zeros(n)
-    sweeps = lib().orc_jacobi_regen(n, seed, kind, gamma, _p(_f64(b)), _p(x), max_sweeps, tol)
-    return x, int(sweeps)
+    if progress is None:
+        sweeps = lib().orc_jacobi_regen(n, seed, kind, gamma, _p(_f64(b)), _p(x), max_sweeps, tol)
+        return x, int(sweeps)
+    bb = _f64(b)
+    d = np.empty(n)
+    lib().orc_diag_all(n, seed, kind, gamma, _p(d))
+    sweeps = 0
+    for sweeps in range(1, max_sweeps + 1):
+        dmax = lib().orc_jacobi_sweep_regen(n, seed, kind, gamma, _p(d), _p(bb), _p(x))
+        progress(sweeps, dmax)
+        if dmax <= tol * np.abs(x).max():
+            break
+    return x, sweeps
 
 
 # ---------------------------------------------------------------- GMRES-IR

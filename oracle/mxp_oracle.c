@@ -407,34 +407,51 @@ double orc_hpl_eta_regen(int64_t n, uint64_t seed, int kind, double gamma, const
  * Stops when the update is at most tol * ||x||_inf or after max_sweeps.
  * Returns the sweeps done.
  */
-int64_t orc_jacobi_regen(int64_t n, uint64_t seed, int kind, double gamma, const double *b, double *x,
-                         int64_t max_sweeps, double tol)
+/* the diagonal A[i,i] of every row, d[n] */
+void orc_diag_all(int64_t n, uint64_t seed, int kind, double gamma, double *d)
 {
     orc_gen g = {n, seed, kind, gamma};
-    double *d = (double *)malloc((size_t)n * sizeof(double));
-    double *xn = (double *)malloc((size_t)n * sizeof(double));
-    int64_t sweeps = 0;
-    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i)
         d[i] = gen_diag(&g, i);
-    for (; sweeps < max_sweeps;) {
-        double dmax = 0.0;
+}
+
+/* One Jacobi sweep from x, in place: x_i <- (b_i - sum_{j != i} A_ij x_j) / d_i
+ * with the off-diagonal entries regenerated and d the diagonal
+ * (orc_diag_all); returns max_i |x_new_i - x_old_i|. */
+double orc_jacobi_sweep_regen(int64_t n, uint64_t seed, int kind, double gamma, const double *d, const double *b,
+                              double *x)
+{
+    orc_gen g = {n, seed, kind, gamma};
+    double *xn = (double *)malloc((size_t)n * sizeof(double));
+    double dmax = 0.0;
 #pragma omp parallel for schedule(static) reduction(max : dmax)
-        for (int64_t i = 0; i < n; ++i) {
-            double off = 0.0;
-            for (int64_t j = 0; j < n; ++j)
-                if (j != i) off += gen_offdiag(&g, i, j) * x[j];
-            xn[i] = (b[i] - off) / d[i];
-            double u = fabs(xn[i] - x[i]);
-            if (u > dmax) dmax = u;
-        }
-        memcpy(x, xn, (size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; ++i) {
+        double off = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            if (j != i) off += gen_offdiag(&g, i, j) * x[j];
+        xn[i] = (b[i] - off) / d[i];
+        double u = fabs(xn[i] - x[i]);
+        if (u > dmax) dmax = u;
+    }
+    memcpy(x, xn, (size_t)n * sizeof(double));
+    free(xn);
+    return dmax;
+}
+
+int64_t orc_jacobi_regen(int64_t n, uint64_t seed, int kind, double gamma, const double *b, double *x,
+                         int64_t max_sweeps, double tol)
+{
+    double *d = (double *)malloc((size_t)n * sizeof(double));
+    int64_t sweeps = 0;
+    for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+    orc_diag_all(n, seed, kind, gamma, d);
+    while (sweeps < max_sweeps) {
+        const double dmax = orc_jacobi_sweep_regen(n, seed, kind, gamma, d, b, x);
         ++sweeps;
         if (dmax <= tol * norm_inf_vec(n, x)) break;
     }
     free(d);
-    free(xn);
     return sweeps;
 }
 

@@ -17,6 +17,7 @@ computed once per size.  Sampled rows of the GPU's own regenerated residual
 are also checked against the oracle's.
 """
 import functools
+import sys
 import gc
 
 import numpy as np
@@ -44,14 +45,24 @@ def _release():
     torch.cuda.empty_cache()
 
 
+def _say(msg):
+    # the oracle's long CPU passes at these sizes report as they finish, on
+    # the process's own stderr (pytest holds a test's captured output until
+    # the test ends)
+    print(msg, file=sys.__stderr__, flush=True)
+
+
 @functools.lru_cache(maxsize=None)
 def _oracle_solution(n, seed):
     """Jacobi solution and ||A||_inf of the oracle (computed once per size)"""
     b = oracle.generate_rhs(n, 1, seed)[:, 0]
-    x, sweeps = oracle.jacobi_regen(n, seed, b, max_sweeps=60)
+    x, sweeps = oracle.jacobi_regen(n, seed, b, max_sweeps=60,
+                                    progress=lambda k, dmax: _say("  oracle n=%d: jacobi sweep %d, largest change %.3g"
+                                                                  % (n, k, dmax)))
     assert sweeps < 60
-    print("  oracle: jacobi sweeps %d" % sweeps, flush=True)
-    return x, b, oracle.anorm_inf_regen(n, seed)
+    a_inf = oracle.anorm_inf_regen(n, seed)
+    _say("  oracle n=%d: ||A||_inf done" % n)
+    return x, b, a_inf
 
 
 def _check_sampled_rows(prob, x, nsample=96):
@@ -74,6 +85,7 @@ def _check_against_oracle(n, seed, prob, res):
     assert np.array_equal(prob.B[0].cpu().numpy(), b)
     err = np.abs(x - xo).max() / np.abs(xo).max()
     eta = oracle.hpl_eta_regen(n, seed, x, b, a_inf=a_inf)
+    _say("  oracle n=%d: eta of the GPU solution done" % n)
     print("  iters %d eta(gpu) %.3g eta(oracle) %.3g, max rel err vs oracle %.3g"
           % (res.iters[0], res.eta[0], eta, err), flush=True)
     assert err <= 1e-12

@@ -142,6 +142,31 @@ def test_jacobi_regen_matches_lu_and_residual_regen_matches_dense():
     assert oracle.hpl_eta_regen(n, seed, xb, b) == pytest.approx(oracle.hpl_eta(A, xb, b), rel=1e-3)
 
 
+def test_jacobi_sweep_by_sweep_equals_the_single_call():
+    # the sweep-at-a-time form (progress reported) is the same iteration:
+    # bit-equal solution and sweep count, and every sweep's largest change
+    # is the distance between the iterates it was given and returned
+    n, seed = 200, 37
+    A, b = _system(n, seed)
+    x1, s1 = oracle.jacobi_regen(n, seed, b)
+    seen = []
+    x2, s2 = oracle.jacobi_regen(n, seed, b, progress=lambda k, dmax: seen.append((k, dmax)))
+    assert s1 == s2 == len(seen) and [k for k, _ in seen] == list(range(1, s1 + 1))
+    assert np.array_equal(x1, x2)
+    # the diagonal the sweeps divide by is the generator's diagonal
+    d = np.empty(n)
+    oracle.lib().orc_diag_all(n, seed, oracle.GEN_DOMINANT, 0.0, oracle._p(d))
+    assert np.array_equal(d, np.diag(A))
+    # one sweep from x is x + D^-1 (b - A x), and its reported change is the update's max norm
+    x = np.random.default_rng(2).uniform(-1, 1, n)
+    y = x.copy()
+    dmax = oracle.lib().orc_jacobi_sweep_regen(n, seed, oracle.GEN_DOMINANT, 0.0, oracle._p(d), oracle._p(b),
+                                               oracle._p(y))
+    want = x + (b - A @ x) / np.diag(A)
+    assert np.abs(y - want).max() <= 1e-13 * np.abs(want).max()
+    assert dmax == np.abs(y - x).max()
+
+
 def test_residual_rows_are_the_dense_residual_on_the_sampled_rows():
     # sampled rows of b - A x with A regenerated, against the dense product
     n, seed = 300, 17
