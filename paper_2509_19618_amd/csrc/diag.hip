@@ -648,6 +648,11 @@ __global__ __launch_bounds__(DT, 2) void k_diag_lu(const DiagGroup grp) {
 size_t diag_lu_smem() { return (size_t)(2 * DW) * TILE_F * sizeof(float); }
 size_t diag_sync_words() { return 1 + 2 * NPMAX; }
 
+// most work-groups cooperating on one diagonal block
+#ifndef MXP_DIAG_WGS
+#define MXP_DIAG_WGS 24
+#endif
+
 template <int ST>
 static hipError_t diag_lu_typed(const DiagCall* calls, int count, hipStream_t s) {
     static const hipError_t attr = hipFuncSetAttribute((const void*)k_diag_lu<ST>,
@@ -664,9 +669,10 @@ static hipError_t diag_lu_typed(const DiagCall* calls, int count, hipStream_t s)
         // most 24 (a 512 block: one leader work-group and 23 helpers; its
         // early update phases have up to 224 tile tasks).  Measured at
         // n = 32768: 16 / 24 / 32 work-groups 45.1 / 44.8 / 45.1 ms for the
-        // factorisation
+        // factorisation; with the unrolled leaf 421.9 / 421.7 / 418.3
+        // TFLOP/s for the solve (mean of two, one box)
         const int P = c.kbp / 32;
-        g.wgs = P < 1 ? 1 : (2 * P > 24 ? 24 : 2 * P);
+        g.wgs = P < 1 ? 1 : (2 * P > MXP_DIAG_WGS ? MXP_DIAG_WGS : 2 * P);
         wmax = g.wgs > wmax ? g.wgs : wmax;
     }
     grp.count = count;
