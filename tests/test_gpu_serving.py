@@ -93,3 +93,24 @@ def test_autotuned_block_sizes():
             res = srv.wait(rid)
             assert res.status == mxp.OK and res.eta < 16
             assert res.nb == srv.block_size(res.n)
+
+
+def test_saturated_mix_every_request_valid():
+    # every request queued at once (eight slots, three worker streams): the
+    # groups' factorisations and the requests' refinements overlap on the
+    # device the whole time.  Every request must succeed with eta < 16 in
+    # the usual few iterations -- an expired wait of a kernel that waits on
+    # other work-groups would fail its request (and stall the server)
+    print("serving: saturated mix", flush=True)
+    rng = np.random.default_rng(11)
+    ns = np.floor(np.exp(rng.uniform(np.log(512), np.log(8192), 150))).astype(int)
+    rs = rng.integers(1, 9, 150)
+    arena = int(1.25 * 8 * mxp.server_request_bytes(8192, 8, 512))
+    with mxp.Server(arena, max_slots=8, nb=512) as srv:
+        ids = [srv.submit(int(n), int(r), 5000 + k, want_x=False) for k, (n, r) in enumerate(zip(ns, rs))]
+        srv.drain()
+        res = [srv.wait(i) for i in ids]
+        st = srv.stats()
+    bad = [(x.n, x.nrhs, x.status, x.iters) for x in res if x.status != mxp.OK or not x.eta < 16 or x.iters > 10]
+    assert not bad, bad
+    assert st["failed"] == 0 and st["completed"] == 150 and st["peak_in_flight"] >= 4
